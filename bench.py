@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of forward CSR SpMM (C = A B) on one MI355X.
+
+Workload (default): the power-law matrix - m = k = 1,000,000, Zipf-2.1 row
+lengths with mean 16 capped at 100,000, uniform random columns, values N(0,1)
+- times B with n = 64 columns, uniform[-1, 1), all float32, synthetic and
+seeded. The plan (kernel choice by timing, merge-path partition) is built
+once before the timed region, as A's structure is fixed across steps; each
+step is one full product (main kernel plus, for merge-based plans, the
+carry-out fix-up pass).
+
+Prints one JSON line: GFLOP/s = 2 nnz n / t over K timed steps, the roofline
+of the main kernel (algorithmic bytes per launch over its event-timed
+duration against 8 TB/s HBM), HBM traffic from committed rocprofv3 counters
+when they match the current kernel sources, and the FP64 CPU oracle timed on
+this host's cores as a baseline.
+"""
+import argparse
+import ctypes
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1803_08601_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+class HipEvents:
+    """Raw hipEvents from the HIP runtime, so that the library can record them
+    around its main kernel on the stream it launches on."""
+
+    def __init__(self):
+        self.L = ctypes.CDLL("libamdhip64.so")
+        self.L.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.L.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                               ctypes.c_void_p]
+        self.L.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        e = ctypes.c_void_p()
+        assert self.L.hipEventCreate(ctypes.byref(e)) == 0
+        return e
+
+    def elapsed_ms(self, a, b):
+        ms = ctypes.c_float()
+        assert self.L.hipEventElapsedTime(ctypes.byref(ms), a, b) == 0
+        return ms.value
+
+    def destroy(self, e):
+        self.L.hipEventDestroy(e)
+
+
+def bytes_min(m, k, nnz, n, sv, sb):
+    """Compulsory traffic: row offsets, column indices and values of A once,
+    B once, C written once."""
+    return 4 * (m + 1) + (4 + sv) * nnz + sb * k * n + 4 * m * n
+
+
+def make_workload(name, n):
+    from paper_1803_08601_amd import workloads as wl
+    if name == "powerlaw":
+        A = wl.power_law(seed=1002)
+        desc = f"power-law CSR 1M x 1M, Zipf 2.1 row lengths mean 16 cap 1e5, n={n}"
+    elif name == "stencil":
+        A = wl.stencil27(seed=1003)
+        desc = f"27-point stencil CSR on 128^3 grid, n={n}"
+    elif name == "plain":
+        A = wl.plain(seed=1001)
+        desc = f"uniform CSR 4096 x 4096, 16 per row, n={n}"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    B = wl.dense({"powerlaw": 1002, "stencil": 1003, "plain": 1001}[name], A.k, n)
+    return A, B, desc
+
+
+def cpu_baseline(A, B, n, budget_s=10.0, max_reps=8):
+    import numpy as np
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    times = []
+    t_start = time.perf_counter()
+    while len(times) < max_reps and (time.perf_counter() - t_start < budget_s or len(times) < 2):
+        t0 = time.perf_counter()
+        oracle.spmm(A.rowptr, A.colind, A.vals, B, n=n, nthreads=threads)
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    return {"value": 2.0 * A.nnz * n / t / 1e9, "unit": "GFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full workload, {len(times)} passes of the FP64 oracle (OpenMP over rows, "
+                      f"{threads} threads), median {t * 1e3:.1f} ms per pass"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="powerlaw", choices=["powerlaw", "stencil", "plain"])
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--mode", default="autotune", choices=["autotune", "paper", "rowsplit", "merge"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1803_08601_amd import native as nv
+
+    if args.copy_calibration:
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": a.numel() * 4}))
+        return
+
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[args.dtype]
+    A, B, desc = make_workload(args.workload, args.n)
+    n = args.n
+    rp = torch.from_numpy(A.rowptr).cuda()
+    ci = torch.from_numpy(A.colind).cuda()
+    vals = torch.from_numpy(A.vals).to(dt).cuda()
+    Bt = torch.from_numpy(B).to(dt).cuda()
+    C = torch.empty(A.m, n, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    plan = nv.Plan(rp, ci, A.m, A.k, n, ld=n, dtype=nv.dtype_code(dt), mode=args.mode, nnz=A.nnz)
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+    kernel = "merge" if info.config.kernel == nv.SPMM_KERNEL_MERGE else "rowsplit"
+
+    ev = HipEvents()
+    evb = [ev.create() for _ in range(args.steps)]
+    eva = [ev.create() for _ in range(args.steps)]
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.execute(vals, Bt, C)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        nv.spmm_execute_events(plan.handle, vals, Bt, C, evb[i], eva[i], stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms = [ev.elapsed_ms(evb[i], eva[i]) for i in range(args.steps)]
+    for e in evb + eva:
+        ev.destroy(e)
+
+    ms = (t1 - t0) * 1e3 / args.steps
+    flops = 2.0 * A.nnz * n
+    gflops = flops / (ms * 1e-3) / 1e9
+    sv = sb = torch.tensor([], dtype=dt).element_size()
+    bmin = bytes_min(A.m, A.k, A.nnz, n, sv, sb)
+    kavg = float(np.mean(kern_ms))
+    achieved = bmin / (kavg * 1e-3) / 1e9
+
+    traffic = None
+    if os.path.exists(COUNTERS):
+        rec = json.load(open(COUNTERS))
+        key = f"{args.workload}-n{n}-{args.dtype}-{kernel}"
+        r = rec.get(key)
+        if r and r.get("kernel_source_sha") == kernel_source_hash():
+            traffic = (r["fetch_kib"] + r["write_kib"]) * 1024.0 * r["copy_scale"]
+
+    out = {
+        "metric": "SpMM GFLOP/s (2*nnz*n/t)",
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": desc, "m": A.m, "k": A.k, "nnz": A.nnz, "n": n,
+                   "kernel": kernel, "mode": args.mode, "shape": info.config.as_dict(),
+                   "paper_rule_kernel": "merge" if info.paper_choice else "rowsplit",
+                   "plan_build_s": round(plan_s, 3), "input_sha": A.digest()},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_merge" if kernel == "merge" else "k_rowsplit",
+                     "kernel_ms": round(kavg, 4), "algorithmic_bytes": bmin},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, B, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

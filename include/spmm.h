@@ -1,0 +1,243 @@
+/*
+ * spmm.h - C ABI of the MI355X (gfx950) CSR sparse x dense matrix multiply.
+ *
+ * Operation (paper Sec. 1; input/output statement of Algorithm 1):
+ *   A is m-by-k in CSR: A_rowptr[m+1] (int32 offsets, A_rowptr[0] = 0,
+ *   non-decreasing), A_colind[nnz] (int32, 0 <= c < k; need not be sorted;
+ *   duplicates are summed), A_vals[nnz].
+ *   B is k-by-n dense, row-major, row stride ld elements.
+ *   C is m-by-n dense, row-major, row stride ld elements, float32.
+ *   C = A * B, i.e. C[i,c] = sum over p in [rowptr[i], rowptr[i+1]) of
+ *   vals[p] * B[colind[p], c]. C is overwritten (never accumulated into);
+ *   rows of A without entries give exact zeros. Sums run in float32 in an
+ *   order fixed by the plan, so repeated calls give bitwise equal results.
+ *
+ * Storage types: vals and B share one type - float32, bfloat16 or float16
+ * (16-bit types as their bit patterns); they are widened exactly to float32
+ * and accumulated in float32. C, dC and dB are always float32.
+ *
+ * Pointers: every pointer argument is a DEVICE pointer unless its name ends
+ * in _host. The caller owns A, B, C and every other array it passes; the
+ * library owns plans and batches and the device workspace inside them
+ * (allocated at create time, freed at destroy). C must not alias A, B or a
+ * plan's workspace.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream). Execute calls only enqueue kernels on it: they allocate nothing
+ * and never synchronise the host, so they may be captured into a hipGraph.
+ * Create/build calls may allocate and synchronise.
+ *
+ * Errors: every call returns an int status (spmm_status). Nothing aborts or
+ * throws across the ABI. spmm_last_error() returns a thread-local message
+ * for the last failing call on this thread. Argument checks happen on the
+ * host before any launch; kernel launch failures are reported as
+ * SPMM_ERR_HIP. The CSR structure itself (monotone rowptr, colind in range)
+ * is the caller's contract and is not checked by execute calls;
+ * spmm_csr_validate() checks it on request.
+ *
+ * Alignment: for 16-byte vector access the library checks B, C, dC, dB and
+ * ld; when they are not aligned it falls back to element access on its own
+ * (no error).
+ */
+#ifndef SPMM_MI355X_H
+#define SPMM_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spmm_status {
+    SPMM_OK = 0,
+    SPMM_ERR_INVALID = -1,     /* bad argument (null pointer, negative size, ld < n, ...) */
+    SPMM_ERR_UNSUPPORTED = -2, /* valid but not supported (dtype, config) */
+    SPMM_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+    SPMM_ERR_NOMEM = -4,       /* device or host allocation failed */
+    SPMM_ERR_STATE = -5        /* destroyed/foreign handle, or call not allowed now */
+} spmm_status;
+
+typedef enum spmm_dtype { SPMM_F32 = 0, SPMM_BF16 = 1, SPMM_F16 = 2 } spmm_dtype;
+
+/* How a plan chooses its kernel.
+ *   PAPER    : the mean-row-length rule of Sec. 5.4 - merge-based when
+ *              nnz / m < 9.35, row split otherwise (compared exactly as
+ *              100 * nnz < 935 * m).
+ *   AUTOTUNE : time the candidate kernels and shapes on scratch buffers of
+ *              the plan's sizes and keep the fastest.
+ *   ROWSPLIT / MERGE : force that kernel with default shapes. */
+typedef enum spmm_mode {
+    SPMM_MODE_PAPER = 0,
+    SPMM_MODE_AUTOTUNE = 1,
+    SPMM_MODE_ROWSPLIT = 2,
+    SPMM_MODE_MERGE = 3
+} spmm_mode;
+
+typedef enum spmm_kernel { SPMM_KERNEL_ROWSPLIT = 0, SPMM_KERNEL_MERGE = 1 } spmm_kernel;
+
+/* Kernel shape. A zero field means "choose automatically". */
+typedef struct spmm_config {
+    int32_t kernel;        /* spmm_kernel */
+    int32_t vec;           /* elements per lane per B-row access: 1, or the 16-byte width
+                              (4 for float32, 8 for 16-bit types) */
+    int32_t lanes_per_row; /* row split (Sec. 4.1): lanes of a wavefront sharing one row of A,
+                              a power of two from the lanes one B row needs up to 64 */
+    int32_t unroll;        /* B-row gathers in flight per lane group: 1, 2, 4 or 8 */
+    int32_t items_per_wg;  /* merge-based (Sec. 4.2): merge items (rows + nonzeros) per
+                              workgroup, 64 .. 8192 */
+} spmm_config;
+
+typedef struct spmm_plan_info {
+    int64_t m, k, nnz, n, ld;
+    int32_t dtype;         /* spmm_dtype */
+    int32_t mode;          /* spmm_mode the plan was created with */
+    int32_t paper_choice;  /* kernel the Sec. 5.4 rule picks for this matrix */
+    spmm_config config;    /* the shape that execute calls use */
+    int32_t lanes_per_slot;/* lanes that cover one B row (or one 64*vec column tile) */
+    int32_t col_tiles;     /* column tiles (grid y) */
+    int64_t num_parts;     /* merge-based: workgroups P (coordinates hold P + 1 pairs) */
+    int64_t max_row_len;   /* longest row (from the device row statistics) */
+    double mean_row_len;   /* nnz / m */
+    double tuned_ms;       /* AUTOTUNE: median time of the chosen candidate, else 0 */
+    int32_t has_transpose; /* spmm_transpose_build has run */
+} spmm_plan_info;
+
+typedef struct spmm_plan_s* spmm_plan_t;
+typedef struct spmm_batch_s* spmm_batch_t;
+
+/* ---------------------------------------------------------------- one call
+ * C = A * B in float32 (Sec. 1). Uses an internal plan cache keyed by
+ * (A_rowptr, A_colind, m, k, n, ld, device); on a miss it reads
+ * A_rowptr[m] back to the host (one 4-byte copy and a stream sync, so this
+ * call is not capture-safe on a miss) and plans in PAPER mode. The structure
+ * behind a cached (A_rowptr, A_colind) pair must not change; call
+ * spmm_cache_clear() after changing it. Returns SPMM_OK for m == 0 or n == 0
+ * without touching memory. */
+int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_vals,
+             const float* B, float* C, int64_t m, int64_t k, int64_t n, int64_t ld,
+             void* stream);
+
+/* Drop every cached plan of spmm_csr (frees their workspace). */
+int spmm_cache_clear(void);
+
+/* ---------------------------------------------------------------- plans
+ * Create a plan for the structure (A_rowptr, A_colind) with nnz nonzeros
+ * (nnz must equal A_rowptr[m]; given by the caller so no read-back is
+ * needed), output width n, row stride ld (shared by B and C), storage type
+ * dtype and kernel choice mode. The plan keeps the two structure pointers;
+ * they must stay valid and unchanged while the plan lives. Creation runs a
+ * device row-statistics pass and, for merge-based plans, the Phase 1
+ * partition of Algorithm 1 (the merge-path coordinates of Sec. 4); it
+ * synchronises `stream`. AUTOTUNE additionally allocates scratch B/C/vals of
+ * the plan's sizes, times the candidates and frees the scratch. */
+int spmm_plan_create(spmm_plan_t* out_plan, const int32_t* A_rowptr, const int32_t* A_colind,
+                     int64_t m, int64_t k, int64_t nnz, int64_t n, int64_t ld,
+                     int32_t dtype, int32_t mode, void* stream);
+
+/* Same, with an explicit kernel shape (zero fields are filled in). */
+int spmm_plan_create_config(spmm_plan_t* out_plan, const int32_t* A_rowptr,
+                            const int32_t* A_colind, int64_t m, int64_t k, int64_t nnz,
+                            int64_t n, int64_t ld, int32_t dtype, const spmm_config* config_host,
+                            void* stream);
+
+/* C = A * B with the plan's kernel: row split (Sec. 4.1) or merge-based
+ * Phases 2-3 of Algorithm 1 (Sec. 4.2). A_vals and B are of the plan's
+ * dtype; C is float32. Enqueue only. */
+int spmm_execute(spmm_plan_t plan, const void* A_vals, const void* B, float* C, void* stream);
+
+/* The same as spmm_execute, for measurement: records the caller's events
+ * ev_before / ev_after (hipEvent_t as void*, may be NULL) on `stream`
+ * immediately before and after the launch of the main kernel (row split,
+ * or Phase 2 of the merge-based kernel; the merge fix-up pass follows
+ * ev_after), so their elapsed time is that kernel's duration. */
+int spmm_execute_events(spmm_plan_t plan, const void* A_vals, const void* B, float* C,
+                        void* ev_before, void* ev_after, void* stream);
+
+/* Plan facts for the host (sizes, the chosen config, Sec. 5.4 choice). */
+int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info_host);
+
+/* Merge-based plans: copy the P + 1 merge-path coordinates (i_p, j_p) for
+ * diagonals min(p * W, m + nnz) into coords_host (2 * (P + 1) int32,
+ * interleaved i, j). cap is the capacity in pairs. Synchronous.
+ * SPMM_ERR_STATE for row-split plans. */
+int spmm_plan_partition(spmm_plan_t plan, int32_t* coords_host, int64_t cap);
+
+/* Free the plan and its workspace (after the work queued with it is done:
+ * the call synchronises the device). */
+int spmm_plan_destroy(spmm_plan_t plan);
+
+/* ---------------------------------------------------------------- backward
+ * Gradients of L = <dC, A B> (not in the paper; A^T products are named as
+ * future work in Sec. 6): dB = A^T dC and dvals = SDDMM(dC, B) on A's
+ * pattern.
+ *
+ * spmm_transpose_build: build, once per structure, the CSR of A^T
+ * (k rows, m columns): AT_rowptr[k+1], AT_colind[nnz] holding the row ids of
+ * A in increasing order within each row of A^T, and perm[nnz] with
+ * AT_vals[q] = A_vals[perm[q]]. Stored in the plan; allocates; synchronises. */
+int spmm_transpose_build(spmm_plan_t plan, void* stream);
+
+/* Copy the transpose into caller buffers (device pointers: k + 1, nnz, nnz
+ * int32). Enqueue only. SPMM_ERR_STATE before spmm_transpose_build. */
+int spmm_transpose_get(spmm_plan_t plan, int32_t* AT_rowptr, int32_t* AT_colind, int32_t* perm,
+                       void* stream);
+
+/* dB (k-by-n, stride ld, float32) = A^T * dC (m-by-n, stride ld, float32):
+ * gathers AT_vals = A_vals[perm] into plan workspace and runs the forward
+ * kernels on (A^T, dC). Requires spmm_transpose_build. Enqueue only. */
+int spmm_execute_t(spmm_plan_t plan, const void* A_vals, const float* dC, float* dB,
+                   void* stream);
+
+/* dvals[p] = sum_c dC[row(p), c] * B[colind[p], c] for every stored entry
+ * p of A (float32 out, nnz entries). dC is float32, B of the plan's dtype.
+ * Enqueue only. */
+int spmm_sddmm(spmm_plan_t plan, const float* dC, const void* B, float* dvals, void* stream);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent products C_b = A_b * B_b of uneven sizes in one
+ * persistent kernel launch (plus one fix-up launch for merge-based
+ * problems), captured once into a hipGraph and replayed by spmm_batch_run.
+ * Each problem's kernel and shape comes from its own plan (mode as in
+ * spmm_plan_create; AUTOTUNE times each problem on its own buffers, which
+ * overwrites C_b). All problems share dtype. The problem array is copied;
+ * the device buffers it names must stay valid while the batch lives. */
+typedef struct spmm_problem {
+    const int32_t* A_rowptr;
+    const int32_t* A_colind;
+    const void* A_vals;
+    const void* B;
+    float* C;
+    int64_t m, k, nnz, n, ld;
+} spmm_problem;
+
+int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, int64_t count,
+                    int32_t dtype, int32_t mode, void* stream);
+
+/* Launch the captured graph on `stream`: all products of the batch. */
+int spmm_batch_run(spmm_batch_t batch, void* stream);
+
+/* The same work without the graph: direct kernel launches on `stream`. */
+int spmm_batch_run_direct(spmm_batch_t batch, void* stream);
+
+/* Per-problem chosen config (problem index b). */
+int spmm_batch_problem_config(spmm_batch_t batch, int64_t b, spmm_config* config_host);
+
+int spmm_batch_destroy(spmm_batch_t batch);
+
+/* ---------------------------------------------------------------- misc */
+/* Check CSR validity on the device: rowptr[0] == 0, non-decreasing,
+ * rowptr[m] == nnz, 0 <= colind < k. Synchronous. SPMM_OK or
+ * SPMM_ERR_INVALID (message in spmm_last_error). */
+int spmm_csr_validate(const int32_t* A_rowptr, const int32_t* A_colind, int64_t m, int64_t k,
+                      int64_t nnz, void* stream);
+
+const char* spmm_status_string(int status);
+const char* spmm_last_error(void);
+/* Library version, e.g. "0.1.0". */
+const char* spmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMM_MI355X_H */

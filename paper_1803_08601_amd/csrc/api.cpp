@@ -1,0 +1,608 @@
+// C ABI of the library: argument checks, plans (kernel choice by the Sec. 5.4
+// rule or by timing), the merge-path workspace, the one-call entry point with
+// its plan cache, and CSR validation. See include/spmm.h for the contract.
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace spmmh {
+
+static thread_local std::string t_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SPMM_ERR_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+static std::mutex g_mu;
+static std::set<const spmm_plan_s*> g_plans;
+
+bool plan_alive(const spmm_plan_s* p) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return p && g_plans.count(p);
+}
+
+int elem_bytes(int dtype) { return dtype == SPMM_F32 ? 4 : 2; }
+int vec16(int dtype) { return dtype == SPMM_F32 ? 4 : 8; }
+
+static int ilog2_ceil(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+// Lanes that cover one B row (capped at a wavefront; wider rows use column
+// tiles) and the resulting number of column tiles.
+static void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles) {
+    int64_t lanes = (n + vec - 1) / vec;
+    if (lanes < 1) lanes = 1;
+    if (lanes > spmmk::kWaveSize) lanes = spmmk::kWaveSize;
+    *g_log2 = ilog2_ceil(lanes);
+    const int64_t span = int64_t(vec) << *g_log2;
+    *col_tiles = (int)((n + span - 1) / span);
+    if (*col_tiles < 1) *col_tiles = 1;
+}
+
+spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec) {
+    spmmk::Shape s;
+    s.vec = vec;
+    slot_geometry(p.n, vec, &s.g_log2, &s.col_tiles);
+    int lpr = std::max<int>(p.cfg.lanes_per_row, 1 << s.g_log2);
+    lpr = std::min(lpr, spmmk::kWaveSize);
+    s.ts_log2 = ilog2_ceil(lpr) - s.g_log2;
+    s.unroll = p.cfg.unroll;
+    s.W = p.cfg.items_per_wg;
+    return s;
+}
+
+static bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
+
+static size_t lds_limit() {
+    static size_t lim = 0;
+    if (!lim) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            lim = prop.sharedMemPerBlock;
+        if (!lim) lim = 65536;
+    }
+    return lim;
+}
+
+int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const void* vals,
+            const void* B, float* C, hipStream_t st, hipEvent_t ev_before, hipEvent_t ev_after) {
+    if (p.m == 0 || p.n == 0) return SPMM_OK;
+    int vec = p.cfg.vec;
+    if (vec != 1 && (!aligned16(B) || !aligned16(C))) vec = 1;
+    const spmmk::Shape s = resolve_shape(p, vec);
+    hipError_t e;
+    if (ev_before) SPMM_HIP(hipEventRecord(ev_before, st));
+    if (p.cfg.kernel == SPMM_KERNEL_ROWSPLIT) {
+        e = spmmk::launch_rowsplit(p.dtype, s, rowptr, colind, vals, B, C, p.m, p.n, p.ld, st);
+        if (e != hipSuccess) return hip_fail(e, "row-split launch");
+        if (ev_after) SPMM_HIP(hipEventRecord(ev_after, st));
+    } else {
+        if (!p.ws.coords) return fail(SPMM_ERR_STATE, "merge plan without partition");
+        e = spmmk::launch_merge(p.dtype, s, rowptr, colind, vals, B, C, p.m, p.n, p.ld,
+                                p.ws.coords, p.ws.P, p.ws.carry_vals, p.ws.carry_rows, st);
+        if (e != hipSuccess) return hip_fail(e, "merge launch");
+        if (ev_after) SPMM_HIP(hipEventRecord(ev_after, st));
+        e = spmmk::launch_merge_fixup(C, p.ld, p.n, p.ws.carry_vals, p.ws.carry_rows, p.ws.P, st);
+        if (e != hipSuccess) return hip_fail(e, "merge fix-up launch");
+    }
+    return SPMM_OK;
+}
+
+static void free_ws(MergeWs& ws) {
+    if (ws.coords) (void)hipFree(ws.coords);
+    if (ws.carry_vals) (void)hipFree(ws.carry_vals);
+    if (ws.carry_rows) (void)hipFree(ws.carry_rows);
+    ws = MergeWs{};
+}
+
+// Allocate (if needed) and fill the merge workspace for W items per piece.
+static int prepare_merge(const spmm_plan_s& p, MergeWs& ws, int W, hipStream_t st) {
+    const int64_t P = (p.m + p.nnz + W - 1) / W;
+    if (P > ws.cap_P || p.n > ws.cap_n || !ws.coords) {
+        free_ws(ws);
+        const int64_t capP = std::max<int64_t>(P, 1);
+        const int64_t capn = std::max<int64_t>(p.n, 1);
+        SPMM_HIP(hipMalloc(&ws.coords, sizeof(int) * 2 * (capP + 1)));
+        SPMM_HIP(hipMalloc(&ws.carry_vals, sizeof(float) * capP * capn));
+        SPMM_HIP(hipMalloc(&ws.carry_rows, sizeof(int) * capP));
+        ws.cap_P = capP;
+        ws.cap_n = capn;
+    }
+    ws.P = P;
+    hipError_t e = spmmk::launch_merge_partition(p.rowptr, p.m, p.nnz, W, P, ws.coords, st);
+    if (e != hipSuccess) return hip_fail(e, "merge partition launch");
+    return SPMM_OK;
+}
+
+static int check_config(const spmm_plan_s& p, spmm_config& c) {
+    const int v16 = vec16(p.dtype);
+    const bool can16 = (p.n % v16 == 0) && (p.ld % v16 == 0);
+    if (c.kernel != SPMM_KERNEL_ROWSPLIT && c.kernel != SPMM_KERNEL_MERGE)
+        return fail(SPMM_ERR_INVALID, "config.kernel %d is not a kernel", c.kernel);
+    if (c.vec == 0) c.vec = can16 ? v16 : 1;
+    if (c.vec != 1 && c.vec != v16)
+        return fail(SPMM_ERR_UNSUPPORTED, "config.vec %d: use 1 or %d for this dtype", c.vec, v16);
+    if (c.vec == v16 && !can16)
+        return fail(SPMM_ERR_UNSUPPORTED, "config.vec %d needs n and ld divisible by %d", c.vec, v16);
+    int g_log2, tiles;
+    slot_geometry(p.n, c.vec, &g_log2, &tiles);
+    const int g = 1 << g_log2;
+    if (c.unroll == 0) c.unroll = 4;
+    if (c.unroll != 1 && c.unroll != 2 && c.unroll != 4 && c.unroll != 8)
+        return fail(SPMM_ERR_UNSUPPORTED, "config.unroll %d: use 1, 2, 4 or 8", c.unroll);
+    if (c.lanes_per_row == 0) {
+        // about four entries of an average row per slot
+        const double d = p.m ? double(p.nnz) / double(p.m) : 0.0;
+        int ts = 1;
+        while (ts * 2 * g <= spmmk::kWaveSize && ts * 2 * 4 <= d) ts *= 2;
+        c.lanes_per_row = ts * g;
+    }
+    if (c.lanes_per_row < 1 || c.lanes_per_row > spmmk::kWaveSize ||
+        (c.lanes_per_row & (c.lanes_per_row - 1)))
+        return fail(SPMM_ERR_UNSUPPORTED, "config.lanes_per_row %d: power of two up to 64",
+                    c.lanes_per_row);
+    if (c.lanes_per_row < g) c.lanes_per_row = g;
+    if (c.items_per_wg == 0) {
+        const int slots = spmmk::kBlock / g;
+        c.items_per_wg = std::max(1024, slots * 8);
+    }
+    if (c.items_per_wg < 64 || c.items_per_wg > 8192)
+        return fail(SPMM_ERR_UNSUPPORTED, "config.items_per_wg %d outside 64..8192", c.items_per_wg);
+    if (c.kernel == SPMM_KERNEL_MERGE) {
+        spmmk::Shape s;
+        s.vec = c.vec;
+        s.W = c.items_per_wg;
+        if (spmmk::merge_lds_bytes(p.dtype, s) > lds_limit())
+            return fail(SPMM_ERR_UNSUPPORTED, "items_per_wg %d needs more LDS than a workgroup has",
+                        c.items_per_wg);
+        if ((p.m + p.nnz + c.items_per_wg - 1) / c.items_per_wg >= (int64_t(1) << 31))
+            return fail(SPMM_ERR_UNSUPPORTED, "too many merge pieces");
+    }
+    return SPMM_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+struct TuneKey {
+    int device;
+    int64_t m, k, nnz, n, ld, maxrow, longrows;
+    int dtype;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(device, m, k, nnz, n, ld, maxrow, longrows, dtype) <
+               std::tie(o.device, o.m, o.k, o.nnz, o.n, o.ld, o.maxrow, o.longrows, o.dtype);
+    }
+};
+static std::map<TuneKey, std::pair<spmm_config, double>> g_tuned;
+
+static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p) {
+    std::vector<spmm_config> out;
+    const int v16 = vec16(p.dtype);
+    const int vec = (p.n % v16 == 0 && p.ld % v16 == 0) ? v16 : 1;
+    int g_log2, tiles;
+    slot_geometry(p.n, vec, &g_log2, &tiles);
+    for (int lpr = 1 << g_log2; lpr <= spmmk::kWaveSize; lpr *= 2)
+        for (int u : {2, 4, 8}) out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024});
+    for (int W : {512, 1024, 2048, 4096})
+        for (int u : {2, 4, 8}) out.push_back({SPMM_KERNEL_MERGE, vec, 1 << g_log2, u, W});
+    return out;
+}
+
+static int autotune(spmm_plan_s& p, hipStream_t st) {
+    const TuneKey key{p.device, p.m, p.k, p.nnz, p.n, p.ld, p.max_row_len, p.long_rows, p.dtype};
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            p.cfg = it->second.first;
+            p.tuned_ms = it->second.second;
+            return SPMM_OK;
+        }
+    }
+    if (p.m == 0 || p.n == 0) {
+        p.cfg = spmm_config{p.paper_choice, 0, 0, 0, 0};
+        return check_config(p, p.cfg);
+    }
+    const int eb = elem_bytes(p.dtype);
+    void *vals = nullptr, *B = nullptr;
+    float* C = nullptr;
+    MergeWs ws;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = SPMM_OK;
+    auto cleanup = [&]() {
+        if (vals) (void)hipFree(vals);
+        if (B) (void)hipFree(B);
+        if (C) (void)hipFree(C);
+        free_ws(ws);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+#define TUNE_HIP(call)                                  \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) {                         \
+            rc = hip_fail(e_, #call);                   \
+            cleanup();                                  \
+            return rc;                                  \
+        }                                               \
+    } while (0)
+    if (p.nnz > 0) TUNE_HIP(hipMalloc(&vals, (size_t)eb * p.nnz));
+    if (p.k > 0) TUNE_HIP(hipMalloc(&B, (size_t)eb * p.k * p.ld));
+    TUNE_HIP(hipMalloc(&C, sizeof(float) * p.m * p.ld));
+    if (vals) TUNE_HIP(hipMemsetAsync(vals, 0x3c, (size_t)eb * p.nnz, st));
+    if (B) TUNE_HIP(hipMemsetAsync(B, 0x3c, (size_t)eb * p.k * p.ld, st));
+    TUNE_HIP(hipEventCreate(&e0));
+    TUNE_HIP(hipEventCreate(&e1));
+
+    double best = 1e30;
+    spmm_config best_cfg{};
+    for (spmm_config c : tune_candidates(p)) {
+        spmm_plan_s q = p;  // shallow copy: never destroyed
+        q.ws = MergeWs{};
+        if (check_config(q, c) != SPMM_OK) continue;
+        q.cfg = c;
+        if (c.kernel == SPMM_KERNEL_MERGE) {
+            rc = prepare_merge(q, ws, c.items_per_wg, st);
+            if (rc != SPMM_OK) { cleanup(); return rc; }
+            q.ws = ws;
+        }
+        std::vector<float> times;
+        for (int rep = 0; rep < 4; ++rep) {
+            TUNE_HIP(hipEventRecord(e0, st));
+            rc = forward(q, q.rowptr, q.colind, vals, B, C, st);
+            if (rc != SPMM_OK) { cleanup(); return rc; }
+            TUNE_HIP(hipEventRecord(e1, st));
+            TUNE_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            TUNE_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) times.push_back(ms);
+            if (rep == 0 && ms > 4.0 * best) break;  // clearly slower: skip the timed reps
+        }
+        if (times.empty()) continue;
+        std::sort(times.begin(), times.end());
+        const double med = times[times.size() / 2];
+        if (med < best) {
+            best = med;
+            best_cfg = c;
+        }
+    }
+    cleanup();
+#undef TUNE_HIP
+    if (best >= 1e30) return fail(SPMM_ERR_UNSUPPORTED, "autotune: no candidate ran");
+    p.cfg = best_cfg;
+    p.tuned_ms = best;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned[key] = {best_cfg, best};
+    return SPMM_OK;
+}
+
+// ------------------------------------------------------------------ plans
+
+static int row_stats(spmm_plan_s& p, hipStream_t st) {
+    if (p.m == 0) return SPMM_OK;
+    int* d = nullptr;
+    int h[3] = {0, 0, 1};
+    SPMM_HIP(hipMalloc(&d, sizeof h));
+    hipError_t e = hipMemcpyAsync(d, h, sizeof h, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = spmmk::launch_row_stats(p.rowptr, p.m, d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "row statistics");
+    p.max_row_len = h[0];
+    p.long_rows = h[1];
+    return SPMM_OK;
+}
+
+static int check_dims(int64_t m, int64_t k, int64_t nnz, int64_t n, int64_t ld) {
+    const int64_t lim = (int64_t(1) << 31) - 1;
+    if (m < 0 || k < 0 || nnz < 0 || n < 0)
+        return fail(SPMM_ERR_INVALID, "negative size (m=%lld k=%lld nnz=%lld n=%lld)",
+                    (long long)m, (long long)k, (long long)nnz, (long long)n);
+    if (m > lim || k > lim || nnz > lim || n > lim)
+        return fail(SPMM_ERR_UNSUPPORTED, "sizes must fit int32");
+    if (ld < std::max<int64_t>(1, n))
+        return fail(SPMM_ERR_INVALID, "ld=%lld must be >= max(1, n=%lld)", (long long)ld,
+                    (long long)n);
+    if (m > 0 && nnz > 0 && k == 0) return fail(SPMM_ERR_INVALID, "nnz > 0 with k == 0");
+    return SPMM_OK;
+}
+
+void destroy_plan(spmm_plan_s* p) {
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    free_ws(p->ws);
+    if (p->tr.at_rowptr) (void)hipFree(p->tr.at_rowptr);
+    if (p->tr.at_colind) (void)hipFree(p->tr.at_colind);
+    if (p->tr.perm) (void)hipFree(p->tr.perm);
+    if (p->tr.at_vals) (void)hipFree(p->tr.at_vals);
+    if (p->tplan) destroy_plan(p->tplan);
+    delete p;
+}
+
+int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, int64_t m,
+                int64_t k, int64_t nnz, int64_t n, int64_t ld, int32_t dtype, int32_t mode,
+                const spmm_config* forced, hipStream_t st, bool register_plan) {
+    if (!out) return fail(SPMM_ERR_INVALID, "out_plan is NULL");
+    *out = nullptr;
+    int rc = check_dims(m, k, nnz, n, ld);
+    if (rc) return rc;
+    if (dtype != SPMM_F32 && dtype != SPMM_BF16 && dtype != SPMM_F16)
+        return fail(SPMM_ERR_UNSUPPORTED, "dtype %d", dtype);
+    if (!forced && (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_MERGE))
+        return fail(SPMM_ERR_INVALID, "mode %d", mode);
+    if (m > 0 && !rowptr) return fail(SPMM_ERR_INVALID, "A_rowptr is NULL");
+    if (nnz > 0 && !colind) return fail(SPMM_ERR_INVALID, "A_colind is NULL");
+
+    spmm_plan_s* p = new (std::nothrow) spmm_plan_s;
+    if (!p) return fail(SPMM_ERR_NOMEM, "plan");
+    p->rowptr = rowptr;
+    p->colind = colind;
+    p->m = m; p->k = k; p->nnz = nnz; p->n = n; p->ld = ld;
+    p->dtype = dtype;
+    p->mode = forced ? -1 : mode;
+    // Sec. 5.4: merge-based when the mean row length nnz / m is below 9.35.
+    p->paper_choice = (m > 0 && 100 * nnz < 935 * m) ? SPMM_KERNEL_MERGE : SPMM_KERNEL_ROWSPLIT;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
+
+    rc = row_stats(*p, st);
+    if (rc == SPMM_OK) {
+        if (forced) {
+            p->cfg = *forced;
+            rc = check_config(*p, p->cfg);
+        } else if (mode == SPMM_MODE_AUTOTUNE) {
+            rc = autotune(*p, st);
+        } else {
+            const int kern = mode == SPMM_MODE_PAPER    ? p->paper_choice
+                             : mode == SPMM_MODE_MERGE ? SPMM_KERNEL_MERGE
+                                                        : SPMM_KERNEL_ROWSPLIT;
+            p->cfg = spmm_config{kern, 0, 0, 0, 0};
+            rc = check_config(*p, p->cfg);
+        }
+    }
+    if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_MERGE)
+        rc = prepare_merge(*p, p->ws, p->cfg.items_per_wg, st);
+    if (rc == SPMM_OK) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "plan synchronise");
+    }
+    if (rc != SPMM_OK) {
+        destroy_plan(p);
+        return rc;
+    }
+    if (register_plan) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_plans.insert(p);
+    }
+    *out = p;
+    return SPMM_OK;
+}
+
+// ------------------------------------------------------------------ plan cache
+
+using CacheKey = std::tuple<const void*, const void*, int64_t, int64_t, int64_t, int64_t, int>;
+static std::map<CacheKey, spmm_plan_s*> g_cache;
+static std::vector<CacheKey> g_cache_order;  // least recently used first
+static constexpr size_t kCacheCap = 64;
+
+}  // namespace spmmh
+
+using namespace spmmh;
+
+extern "C" {
+
+const char* spmm_status_string(int status) {
+    switch (status) {
+    case SPMM_OK: return "ok";
+    case SPMM_ERR_INVALID: return "invalid argument";
+    case SPMM_ERR_UNSUPPORTED: return "unsupported";
+    case SPMM_ERR_HIP: return "HIP runtime error";
+    case SPMM_ERR_NOMEM: return "out of memory";
+    case SPMM_ERR_STATE: return "invalid state or handle";
+    default: return "unknown status";
+    }
+}
+
+const char* spmm_last_error(void) { return t_err.c_str(); }
+
+const char* spmm_version(void) { return "0.1.0"; }
+
+int spmm_plan_create(spmm_plan_t* out_plan, const int32_t* A_rowptr, const int32_t* A_colind,
+                     int64_t m, int64_t k, int64_t nnz, int64_t n, int64_t ld, int32_t dtype,
+                     int32_t mode, void* stream) {
+    return create_plan(out_plan, A_rowptr, A_colind, m, k, nnz, n, ld, dtype, mode, nullptr,
+                       static_cast<hipStream_t>(stream), true);
+}
+
+int spmm_plan_create_config(spmm_plan_t* out_plan, const int32_t* A_rowptr,
+                            const int32_t* A_colind, int64_t m, int64_t k, int64_t nnz,
+                            int64_t n, int64_t ld, int32_t dtype, const spmm_config* config_host,
+                            void* stream) {
+    if (!config_host) return fail(SPMM_ERR_INVALID, "config is NULL");
+    return create_plan(out_plan, A_rowptr, A_colind, m, k, nnz, n, ld, dtype, 0, config_host,
+                       static_cast<hipStream_t>(stream), true);
+}
+
+int spmm_execute(spmm_plan_t plan, const void* A_vals, const void* B, float* C, void* stream) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (plan->m == 0 || plan->n == 0) return SPMM_OK;
+    if (!C) return fail(SPMM_ERR_INVALID, "C is NULL");
+    if (plan->nnz > 0 && (!A_vals || !B)) return fail(SPMM_ERR_INVALID, "A_vals or B is NULL");
+    return forward(*plan, plan->rowptr, plan->colind, A_vals, B, C,
+                   static_cast<hipStream_t>(stream));
+}
+
+int spmm_execute_events(spmm_plan_t plan, const void* A_vals, const void* B, float* C,
+                        void* ev_before, void* ev_after, void* stream) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (plan->m == 0 || plan->n == 0) return SPMM_OK;
+    if (!C) return fail(SPMM_ERR_INVALID, "C is NULL");
+    if (plan->nnz > 0 && (!A_vals || !B)) return fail(SPMM_ERR_INVALID, "A_vals or B is NULL");
+    return forward(*plan, plan->rowptr, plan->colind, A_vals, B, C,
+                   static_cast<hipStream_t>(stream), static_cast<hipEvent_t>(ev_before),
+                   static_cast<hipEvent_t>(ev_after));
+}
+
+int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (!info) return fail(SPMM_ERR_INVALID, "info is NULL");
+    memset(info, 0, sizeof *info);
+    info->m = plan->m; info->k = plan->k; info->nnz = plan->nnz; info->n = plan->n;
+    info->ld = plan->ld;
+    info->dtype = plan->dtype;
+    info->mode = plan->mode;
+    info->paper_choice = plan->paper_choice;
+    info->config = plan->cfg;
+    const spmmk::Shape s = resolve_shape(*plan, plan->cfg.vec);
+    info->lanes_per_slot = 1 << s.g_log2;
+    info->col_tiles = s.col_tiles;
+    info->num_parts = plan->cfg.kernel == SPMM_KERNEL_MERGE ? plan->ws.P : 0;
+    info->max_row_len = plan->max_row_len;
+    info->mean_row_len = plan->m ? double(plan->nnz) / double(plan->m) : 0.0;
+    info->tuned_ms = plan->tuned_ms;
+    info->has_transpose = plan->tr.at_rowptr != nullptr || (plan->k == 0 && plan->tplan);
+    return SPMM_OK;
+}
+
+int spmm_plan_partition(spmm_plan_t plan, int32_t* coords_host, int64_t cap) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (plan->cfg.kernel != SPMM_KERNEL_MERGE)
+        return fail(SPMM_ERR_STATE, "row-split plan has no merge partition");
+    if (!coords_host) return fail(SPMM_ERR_INVALID, "coords_host is NULL");
+    if (cap < plan->ws.P + 1)
+        return fail(SPMM_ERR_INVALID, "cap %lld < P + 1 = %lld", (long long)cap,
+                    (long long)(plan->ws.P + 1));
+    SPMM_HIP(hipMemcpy(coords_host, plan->ws.coords, sizeof(int) * 2 * (plan->ws.P + 1),
+                       hipMemcpyDeviceToHost));
+    return SPMM_OK;
+}
+
+int spmm_plan_destroy(spmm_plan_t plan) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!plan || !g_plans.count(plan))
+            return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+        g_plans.erase(plan);
+    }
+    destroy_plan(plan);
+    return SPMM_OK;
+}
+
+int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_vals,
+             const float* B, float* C, int64_t m, int64_t k, int64_t n, int64_t ld,
+             void* stream) {
+    int rc = check_dims(m, k, 0, n, ld);
+    if (rc) return rc;
+    if (m == 0 || n == 0) return SPMM_OK;
+    if (!A_rowptr || !C) return fail(SPMM_ERR_INVALID, "A_rowptr or C is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    SPMM_HIP(hipGetDevice(&dev));
+    const CacheKey key{A_rowptr, A_colind, m, k, n, ld, dev};
+    spmm_plan_s* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            p = it->second;
+            auto pos = std::find(g_cache_order.begin(), g_cache_order.end(), key);
+            if (pos != g_cache_order.end()) g_cache_order.erase(pos);
+            g_cache_order.push_back(key);
+        }
+    }
+    if (!p) {
+        int32_t nnz32 = 0;
+        SPMM_HIP(hipMemcpyAsync(&nnz32, A_rowptr + m, sizeof nnz32, hipMemcpyDeviceToHost, st));
+        SPMM_HIP(hipStreamSynchronize(st));
+        if (nnz32 < 0) return fail(SPMM_ERR_INVALID, "A_rowptr[m] < 0");
+        if (nnz32 > 0 && (!A_colind || !A_vals || !B))
+            return fail(SPMM_ERR_INVALID, "A_colind, A_vals or B is NULL");
+        rc = create_plan(&p, A_rowptr, A_colind, m, k, nnz32, n, ld, SPMM_F32, SPMM_MODE_PAPER,
+                         nullptr, st, false);
+        if (rc) return rc;
+        std::vector<spmm_plan_s*> evict;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_cache[key] = p;
+            g_cache_order.push_back(key);
+            while (g_cache_order.size() > kCacheCap) {
+                evict.push_back(g_cache[g_cache_order.front()]);
+                g_cache.erase(g_cache_order.front());
+                g_cache_order.erase(g_cache_order.begin());
+            }
+        }
+        for (auto* q : evict) destroy_plan(q);
+    } else if (p->nnz > 0 && (!A_colind || !A_vals || !B)) {
+        return fail(SPMM_ERR_INVALID, "A_colind, A_vals or B is NULL");
+    }
+    return forward(*p, A_rowptr, A_colind, A_vals, B, C, st);
+}
+
+int spmm_cache_clear(void) {
+    std::vector<spmm_plan_s*> all;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& kv : g_cache) all.push_back(kv.second);
+        g_cache.clear();
+        g_cache_order.clear();
+    }
+    for (auto* p : all) destroy_plan(p);
+    return SPMM_OK;
+}
+
+int spmm_csr_validate(const int32_t* A_rowptr, const int32_t* A_colind, int64_t m, int64_t k,
+                      int64_t nnz, void* stream) {
+    int rc = check_dims(m, k, nnz, 0, 1);
+    if (rc) return rc;
+    if (!A_rowptr) return fail(SPMM_ERR_INVALID, "A_rowptr is NULL");
+    if (nnz > 0 && !A_colind) return fail(SPMM_ERR_INVALID, "A_colind is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int* d = nullptr;
+    int h[4] = {0, 0, 1, 0};
+    SPMM_HIP(hipMalloc(&d, sizeof h));
+    hipError_t e = hipMemcpyAsync(d, h, sizeof h, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && m > 0) e = spmmk::launch_row_stats(A_rowptr, m, d, st);
+    if (e == hipSuccess && nnz > 0) e = spmmk::launch_check_cols(A_colind, nnz, k, d + 3, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, st);
+    int32_t last = 0, first = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&last, A_rowptr + m, sizeof last, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&first, A_rowptr, sizeof first, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "validate");
+    if (first != 0) return fail(SPMM_ERR_INVALID, "A_rowptr[0] = %d, expected 0", first);
+    if (!h[2]) return fail(SPMM_ERR_INVALID, "A_rowptr decreases");
+    if (last != nnz)
+        return fail(SPMM_ERR_INVALID, "A_rowptr[m] = %d but nnz = %lld", last, (long long)nnz);
+    if (h[3]) return fail(SPMM_ERR_INVALID, "a column index is outside [0, k)");
+    return SPMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Device helpers shared by the gfx950 kernels: storage types, 16-byte
+// vector access widened to float32, streaming (non-temporal) access for data
+// that is read or written once, and XCD-aware workgroup numbering.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spmmk {
+
+constexpr int kWave = 64;   // CDNA wavefront width (same as kWaveSize)
+constexpr int kXcds = 8;    // MI355X: 8 accelerator dies, each with its own L2
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Storage types of A's values and B. 16-bit types travel as raw bits and are
+// widened exactly to float32 (bf16: the upper half of a binary32 pattern;
+// fp16: the hardware conversion, exact for every binary16 value).
+struct F32 {
+    using T = float;
+    static constexpr int kVec16 = 4;  // elements per 16-byte access
+};
+struct BF16 {
+    using T = uint16_t;
+    static constexpr int kVec16 = 8;
+};
+struct F16 {
+    using T = uint16_t;
+    static constexpr int kVec16 = 8;
+};
+
+__device__ __forceinline__ float widen_bits(uint32_t h, BF16) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ float widen_bits(uint32_t h, F16) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+}
+
+// One element (A's values).
+__device__ __forceinline__ float load_elem(const float* p, F32) { return __builtin_nontemporal_load(p); }
+template <class S>
+__device__ __forceinline__ float load_elem(const uint16_t* p, S) {
+    return widen_bits(__builtin_nontemporal_load(p), S{});
+}
+
+// Unpack two 16-bit values held in one dword.
+__device__ __forceinline__ void unpack2(uint32_t w, float* o, BF16) {
+    o[0] = __uint_as_float(w << 16);
+    o[1] = __uint_as_float(w & 0xffff0000u);
+}
+__device__ __forceinline__ void unpack2(uint32_t w, float* o, F16) {
+    f16x2 h = __builtin_bit_cast(f16x2, w);
+    o[0] = (float)h.x;
+    o[1] = (float)h.y;
+}
+
+// VEC consecutive elements of a B row (cached load: B rows are reused).
+template <class S, int VEC>
+__device__ __forceinline__ void load_row(const typename S::T* p, float (&o)[VEC]);
+
+template <>
+__device__ __forceinline__ void load_row<F32, 4>(const float* p, float (&o)[4]) {
+    f32x4 v = *reinterpret_cast<const f32x4*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load_row<F32, 1>(const float* p, float (&o)[1]) { o[0] = *p; }
+template <>
+__device__ __forceinline__ void load_row<BF16, 8>(const uint16_t* p, float (&o)[8]) {
+    u32x4 v = *reinterpret_cast<const u32x4*>(p);
+    unpack2(v.x, o + 0, BF16{}); unpack2(v.y, o + 2, BF16{});
+    unpack2(v.z, o + 4, BF16{}); unpack2(v.w, o + 6, BF16{});
+}
+template <>
+__device__ __forceinline__ void load_row<BF16, 1>(const uint16_t* p, float (&o)[1]) {
+    o[0] = widen_bits(*p, BF16{});
+}
+template <>
+__device__ __forceinline__ void load_row<F16, 8>(const uint16_t* p, float (&o)[8]) {
+    u32x4 v = *reinterpret_cast<const u32x4*>(p);
+    unpack2(v.x, o + 0, F16{}); unpack2(v.y, o + 2, F16{});
+    unpack2(v.z, o + 4, F16{}); unpack2(v.w, o + 6, F16{});
+}
+template <>
+__device__ __forceinline__ void load_row<F16, 1>(const uint16_t* p, float (&o)[1]) {
+    o[0] = widen_bits(*p, F16{});
+}
+
+// VEC float32 results to C (streaming store: C is written once).
+template <int VEC>
+__device__ __forceinline__ void store_out(float* p, const float (&a)[VEC]) {
+    if constexpr (VEC % 4 == 0) {
+#pragma unroll
+        for (int e = 0; e < VEC; e += 4) {
+            f32x4 v = {a[e], a[e + 1], a[e + 2], a[e + 3]};
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p + e));
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) __builtin_nontemporal_store(a[e], p + e);
+    }
+}
+
+// Read VEC float32 values (carry-out rows, dC rows).
+template <int VEC>
+__device__ __forceinline__ void load_f32(const float* p, float (&o)[VEC]) {
+    if constexpr (VEC % 4 == 0) {
+#pragma unroll
+        for (int e = 0; e < VEC; e += 4) {
+            f32x4 v = *reinterpret_cast<const f32x4*>(p + e);
+            o[e] = v.x; o[e + 1] = v.y; o[e + 2] = v.z; o[e + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = p[e];
+    }
+}
+
+template <int VEC>
+__device__ __forceinline__ void store_f32(float* p, const float (&a)[VEC]) {
+    if constexpr (VEC % 4 == 0) {
+#pragma unroll
+        for (int e = 0; e < VEC; e += 4) {
+            f32x4 v = {a[e], a[e + 1], a[e + 2], a[e + 3]};
+            *reinterpret_cast<f32x4*>(p + e) = v;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) p[e] = a[e];
+    }
+}
+
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8). Renumber them so that each XCD works on one contiguous range of
+// logical tiles: neighbouring rows then share that XCD's L2. A bijection on
+// [0, nblocks); correctness never depends on the dispatch order.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
+    const uint32_t q = nblocks / kXcds, r = nblocks % kXcds;
+    const uint32_t x = bid % kXcds, idx = bid / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + idx;
+}
+
+}  // namespace spmmk

@@ -1,0 +1,50 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spmmk {
+
+constexpr int kBlock = 256;  // threads per workgroup for every SpMM kernel
+constexpr int kWaveSize = 64;  // CDNA wavefront width
+
+// Launch shape resolved for one call. Lanes of a wavefront are grouped into
+// "slots" of 2^g_log2 lanes; a slot covers vec * 2^g_log2 consecutive columns
+// of one B row (one column tile). Row split groups 2^ts_log2 slots into a
+// team that owns one row of A.
+struct Shape {
+    int vec = 1;
+    int g_log2 = 0;
+    int ts_log2 = 0;
+    int unroll = 4;
+    int W = 1024;       // merge items per workgroup
+    int col_tiles = 1;
+};
+
+hipError_t launch_rowsplit(int dtype, const Shape& s, const int* rowptr, const int* colind,
+                           const void* vals, const void* B, float* C, int64_t m, int64_t n,
+                           int64_t ld, hipStream_t st);
+
+hipError_t launch_merge_partition(const int* rowptr, int64_t m, int64_t nnz, int W, int64_t P,
+                                  int* coords, hipStream_t st);
+
+hipError_t launch_merge(int dtype, const Shape& s, const int* rowptr, const int* colind,
+                        const void* vals, const void* B, float* C, int64_t m, int64_t n,
+                        int64_t ld, const int* coords, int64_t P, float* carry_vals,
+                        int* carry_rows, hipStream_t st);
+
+hipError_t launch_merge_fixup(float* C, int64_t ld, int64_t n, const float* carry_vals,
+                              const int* carry_rows, int64_t P, hipStream_t st);
+
+// stats[0] = longest row, stats[1] = rows with >= 1024 entries,
+// stats[2] = 1 if rowptr is non-decreasing with rowptr[0] == 0 else 0.
+hipError_t launch_row_stats(const int* rowptr, int64_t m, int* stats, hipStream_t st);
+
+// flags[0] = 1 if some colind is outside [0, k).
+hipError_t launch_check_cols(const int* colind, int64_t nnz, int64_t k, int* flags,
+                             hipStream_t st);
+
+size_t merge_lds_bytes(int dtype, const Shape& s);
+
+}  // namespace spmmk

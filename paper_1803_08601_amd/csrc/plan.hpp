@@ -1,0 +1,71 @@
+// Plan object and host helpers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/spmm.h"
+#include "kernels.hpp"
+
+namespace spmmh {
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_fail(hipError_t e, const char* what);
+
+#define SPMM_HIP(call)                                      \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return spmmh::hip_fail(e_, #call); \
+    } while (0)
+
+// Merge-based workspace: P + 1 coordinates, P carry-out rows of n floats and
+// P carry-out row ids.
+struct MergeWs {
+    int* coords = nullptr;
+    float* carry_vals = nullptr;
+    int* carry_rows = nullptr;
+    int64_t P = 0;
+    int64_t cap_P = 0;  // allocated capacity in pieces
+    int64_t cap_n = 0;
+};
+
+struct Transpose {
+    int* at_rowptr = nullptr;
+    int* at_colind = nullptr;
+    int* perm = nullptr;
+    void* at_vals = nullptr;  // gathered values, plan dtype
+};
+
+}  // namespace spmmh
+
+struct spmm_plan_s {
+    const int32_t* rowptr = nullptr;
+    const int32_t* colind = nullptr;
+    int64_t m = 0, k = 0, nnz = 0, n = 0, ld = 0;
+    int32_t dtype = 0, mode = 0, paper_choice = 0;
+    spmm_config cfg{};
+    int64_t max_row_len = 0, long_rows = 0;
+    double tuned_ms = 0.0;
+    int device = 0;
+    spmmh::MergeWs ws;
+    spmmh::Transpose tr;
+    spmm_plan_s* tplan = nullptr;  // plan over A^T (k rows, m columns)
+};
+
+namespace spmmh {
+
+bool plan_alive(const spmm_plan_s* p);
+int elem_bytes(int dtype);
+int vec16(int dtype);
+spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec);
+int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const void* vals,
+            const void* B, float* C, hipStream_t st, hipEvent_t ev_before = nullptr,
+            hipEvent_t ev_after = nullptr);
+int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, int64_t m,
+                int64_t k, int64_t nnz, int64_t n, int64_t ld, int32_t dtype, int32_t mode,
+                const spmm_config* forced, hipStream_t st, bool register_plan);
+void destroy_plan(spmm_plan_s* p);
+
+}  // namespace spmmh

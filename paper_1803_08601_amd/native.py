@@ -1,0 +1,301 @@
+"""ctypes binding of ``libspmm.so`` (include/spmm.h): argument marshalling only.
+
+Functions carry the C names. Tensors supply device pointers (``data_ptr()``)
+and the current HIP stream; every computation runs in the library's kernels.
+There is no fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspmm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "spmm.h")
+
+SPMM_OK, SPMM_ERR_INVALID, SPMM_ERR_UNSUPPORTED, SPMM_ERR_HIP, SPMM_ERR_NOMEM, SPMM_ERR_STATE = \
+    0, -1, -2, -3, -4, -5
+SPMM_F32, SPMM_BF16, SPMM_F16 = 0, 1, 2
+SPMM_MODE_PAPER, SPMM_MODE_AUTOTUNE, SPMM_MODE_ROWSPLIT, SPMM_MODE_MERGE = 0, 1, 2, 3
+SPMM_KERNEL_ROWSPLIT, SPMM_KERNEL_MERGE = 0, 1
+
+MODES = {"paper": SPMM_MODE_PAPER, "autotune": SPMM_MODE_AUTOTUNE,
+         "rowsplit": SPMM_MODE_ROWSPLIT, "merge": SPMM_MODE_MERGE}
+
+
+class spmm_config(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("vec", ctypes.c_int32),
+                ("lanes_per_row", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("items_per_wg", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class spmm_plan_info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("k", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("n", ctypes.c_int64), ("ld", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("paper_choice", ctypes.c_int32),
+                ("config", spmm_config), ("lanes_per_slot", ctypes.c_int32),
+                ("col_tiles", ctypes.c_int32), ("num_parts", ctypes.c_int64),
+                ("max_row_len", ctypes.c_int64), ("mean_row_len", ctypes.c_double),
+                ("tuned_ms", ctypes.c_double), ("has_transpose", ctypes.c_int32)]
+
+
+class spmm_problem(ctypes.Structure):
+    _fields_ = [("A_rowptr", ctypes.c_void_p), ("A_colind", ctypes.c_void_p),
+                ("A_vals", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("m", ctypes.c_int64), ("k", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("n", ctypes.c_int64), ("ld", ctypes.c_int64)]
+
+
+class SpmmError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn}: {status_string(status)} ({status}): {msg}")
+        self.status = status
+
+
+_lib = None
+_VP, _I64, _I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+_SIGS = {
+    "spmm_csr": [_VP, _VP, _VP, _VP, _VP, _I64, _I64, _I64, _I64, _VP],
+    "spmm_cache_clear": [],
+    "spmm_plan_create": [_VP, _VP, _VP, _I64, _I64, _I64, _I64, _I64, _I32, _I32, _VP],
+    "spmm_plan_create_config": [_VP, _VP, _VP, _I64, _I64, _I64, _I64, _I64, _I32, _VP, _VP],
+    "spmm_execute": [_VP, _VP, _VP, _VP, _VP],
+    "spmm_execute_events": [_VP, _VP, _VP, _VP, _VP, _VP, _VP],
+    "spmm_plan_info_get": [_VP, _VP],
+    "spmm_plan_partition": [_VP, _VP, _I64],
+    "spmm_plan_destroy": [_VP],
+    "spmm_transpose_build": [_VP, _VP],
+    "spmm_transpose_get": [_VP, _VP, _VP, _VP, _VP],
+    "spmm_execute_t": [_VP, _VP, _VP, _VP, _VP],
+    "spmm_sddmm": [_VP, _VP, _VP, _VP, _VP],
+    "spmm_batch_plan": [_VP, _VP, _I64, _I32, _I32, _VP],
+    "spmm_batch_run": [_VP, _VP],
+    "spmm_batch_run_direct": [_VP, _VP],
+    "spmm_batch_problem_config": [_VP, _I64, _VP],
+    "spmm_batch_destroy": [_VP],
+    "spmm_csr_validate": [_VP, _VP, _I64, _I64, _I64, _VP],
+    "spmm_status_string": [ctypes.c_int],
+    "spmm_last_error": [],
+    "spmm_version": [],
+}
+_STR_FUNCS = {"spmm_status_string", "spmm_last_error", "spmm_version"}
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name in _STR_FUNCS else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions include/spmm.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(spmm_\w+)\s*\(", text, re.M)))
+
+
+def status_string(status):
+    return lib().spmm_status_string(status).decode()
+
+
+def spmm_last_error():
+    return lib().spmm_last_error().decode()
+
+
+def spmm_version():
+    return lib().spmm_version().decode()
+
+
+def _check(fn, status):
+    if status != SPMM_OK:
+        raise SpmmError(fn, status, spmm_last_error())
+    return status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def dtype_code(torch_dtype):
+    import torch
+    return {torch.float32: SPMM_F32, torch.bfloat16: SPMM_BF16, torch.float16: SPMM_F16}[torch_dtype]
+
+
+# ---------------------------------------------------------------- entry points
+
+def spmm_csr(A_rowptr, A_colind, A_vals, B, C, m, k, n, ld, stream=None):
+    return _check("spmm_csr", lib().spmm_csr(_ptr(A_rowptr), _ptr(A_colind), _ptr(A_vals),
+                                             _ptr(B), _ptr(C), m, k, n, ld, _stream(stream)))
+
+
+def spmm_cache_clear():
+    return _check("spmm_cache_clear", lib().spmm_cache_clear())
+
+
+def spmm_plan_create(A_rowptr, A_colind, m, k, nnz, n, ld, dtype, mode, stream=None):
+    h = ctypes.c_void_p()
+    _check("spmm_plan_create",
+           lib().spmm_plan_create(ctypes.byref(h), _ptr(A_rowptr), _ptr(A_colind), m, k, nnz, n,
+                                  ld, dtype, mode, _stream(stream)))
+    return h
+
+
+def spmm_plan_create_config(A_rowptr, A_colind, m, k, nnz, n, ld, dtype, config, stream=None):
+    h = ctypes.c_void_p()
+    _check("spmm_plan_create_config",
+           lib().spmm_plan_create_config(ctypes.byref(h), _ptr(A_rowptr), _ptr(A_colind), m, k,
+                                         nnz, n, ld, dtype, ctypes.byref(config),
+                                         _stream(stream)))
+    return h
+
+
+def spmm_execute(plan, A_vals, B, C, stream=None):
+    return _check("spmm_execute", lib().spmm_execute(plan, _ptr(A_vals), _ptr(B), _ptr(C),
+                                                     _stream(stream)))
+
+
+def spmm_execute_events(plan, A_vals, B, C, ev_before, ev_after, stream=None):
+    return _check("spmm_execute_events", lib().spmm_execute_events(
+        plan, _ptr(A_vals), _ptr(B), _ptr(C), ev_before, ev_after, _stream(stream)))
+
+
+def spmm_plan_info_get(plan):
+    info = spmm_plan_info()
+    _check("spmm_plan_info_get", lib().spmm_plan_info_get(plan, ctypes.byref(info)))
+    return info
+
+
+def spmm_plan_partition(plan, num_parts):
+    import numpy as np
+    out = np.empty((num_parts + 1, 2), dtype=np.int32)
+    _check("spmm_plan_partition", lib().spmm_plan_partition(
+        plan, out.ctypes.data_as(ctypes.c_void_p), num_parts + 1))
+    return out
+
+
+def spmm_plan_destroy(plan):
+    return _check("spmm_plan_destroy", lib().spmm_plan_destroy(plan))
+
+
+def spmm_transpose_build(plan, stream=None):
+    return _check("spmm_transpose_build", lib().spmm_transpose_build(plan, _stream(stream)))
+
+
+def spmm_transpose_get(plan, AT_rowptr, AT_colind, perm, stream=None):
+    return _check("spmm_transpose_get", lib().spmm_transpose_get(
+        plan, _ptr(AT_rowptr), _ptr(AT_colind), _ptr(perm), _stream(stream)))
+
+
+def spmm_execute_t(plan, A_vals, dC, dB, stream=None):
+    return _check("spmm_execute_t", lib().spmm_execute_t(plan, _ptr(A_vals), _ptr(dC), _ptr(dB),
+                                                         _stream(stream)))
+
+
+def spmm_sddmm(plan, dC, B, dvals, stream=None):
+    return _check("spmm_sddmm", lib().spmm_sddmm(plan, _ptr(dC), _ptr(B), _ptr(dvals),
+                                                 _stream(stream)))
+
+
+def spmm_batch_plan(problems, dtype, mode, stream=None):
+    arr = (spmm_problem * len(problems))(*problems)
+    h = ctypes.c_void_p()
+    _check("spmm_batch_plan", lib().spmm_batch_plan(ctypes.byref(h), arr, len(problems), dtype,
+                                                    mode, _stream(stream)))
+    return h
+
+
+def spmm_batch_run(batch, stream=None):
+    return _check("spmm_batch_run", lib().spmm_batch_run(batch, _stream(stream)))
+
+
+def spmm_batch_run_direct(batch, stream=None):
+    return _check("spmm_batch_run_direct", lib().spmm_batch_run_direct(batch, _stream(stream)))
+
+
+def spmm_batch_problem_config(batch, b):
+    c = spmm_config()
+    _check("spmm_batch_problem_config", lib().spmm_batch_problem_config(batch, b, ctypes.byref(c)))
+    return c
+
+
+def spmm_batch_destroy(batch):
+    return _check("spmm_batch_destroy", lib().spmm_batch_destroy(batch))
+
+
+def spmm_csr_validate(A_rowptr, A_colind, m, k, nnz, stream=None):
+    return _check("spmm_csr_validate", lib().spmm_csr_validate(_ptr(A_rowptr), _ptr(A_colind), m,
+                                                               k, nnz, _stream(stream)))
+
+
+# ---------------------------------------------------------------- plan wrapper
+
+class Plan:
+    """Owns a plan handle for one CSR structure (tensors kept alive here)."""
+
+    def __init__(self, rowptr, colind, m, k, n, ld=None, dtype=SPMM_F32, mode="paper",
+                 config=None, nnz=None, stream=None):
+        self.rowptr, self.colind = rowptr, colind
+        self.m, self.k, self.n = int(m), int(k), int(n)
+        self.ld = int(n if ld is None else ld)
+        self.nnz = int(colind.numel() if nnz is None else nnz)
+        self.dtype = dtype
+        if config is not None:
+            cfg = config if isinstance(config, spmm_config) else spmm_config(**config)
+            self.handle = spmm_plan_create_config(rowptr, colind, self.m, self.k, self.nnz, self.n,
+                                                  self.ld, dtype, cfg, stream)
+        else:
+            self.handle = spmm_plan_create(rowptr, colind, self.m, self.k, self.nnz, self.n,
+                                           self.ld, dtype, MODES.get(mode, mode), stream)
+
+    def info(self):
+        return spmm_plan_info_get(self.handle)
+
+    def execute(self, vals, B, C, stream=None):
+        spmm_execute(self.handle, vals, B, C, stream)
+        return C
+
+    def partition(self):
+        return spmm_plan_partition(self.handle, self.info().num_parts)
+
+    def transpose_build(self, stream=None):
+        spmm_transpose_build(self.handle, stream)
+
+    def execute_t(self, vals, dC, dB, stream=None):
+        spmm_execute_t(self.handle, vals, dC, dB, stream)
+        return dB
+
+    def sddmm(self, dC, B, dvals, stream=None):
+        spmm_sddmm(self.handle, dC, B, dvals, stream)
+        return dvals
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            spmm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,79 @@
+"""The C ABI on the host (no GPU needed): the library loads, exports every
+function include/spmm.h declares, and rejects bad arguments before any HIP
+call."""
+import ctypes
+
+import pytest
+
+from paper_1803_08601_amd import native as nv
+
+
+def test_header_symbols_exported():
+    L = nv.lib()
+    names = nv.header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(nv._SIGS), "binding and header disagree"
+
+
+def test_status_strings_and_version():
+    assert nv.status_string(nv.SPMM_OK) == "ok"
+    assert "invalid" in nv.status_string(nv.SPMM_ERR_INVALID)
+    assert nv.status_string(12345) == "unknown status"
+    assert nv.spmm_version().count(".") == 2
+
+
+def _create(**kw):
+    a = dict(out=ctypes.byref(ctypes.c_void_p()), rowptr=ctypes.c_void_p(8),
+             colind=ctypes.c_void_p(8), m=10, k=10, nnz=20, n=4, ld=4, dtype=0, mode=0)
+    a.update(kw)
+    return nv.lib().spmm_plan_create(a["out"], a["rowptr"], a["colind"], a["m"], a["k"], a["nnz"],
+                                     a["n"], a["ld"], a["dtype"], a["mode"], None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(out=None), nv.SPMM_ERR_INVALID),
+    (dict(m=-1), nv.SPMM_ERR_INVALID),
+    (dict(n=-3), nv.SPMM_ERR_INVALID),
+    (dict(nnz=-1), nv.SPMM_ERR_INVALID),
+    (dict(ld=3), nv.SPMM_ERR_INVALID),
+    (dict(n=0, ld=0), nv.SPMM_ERR_INVALID),
+    (dict(dtype=7), nv.SPMM_ERR_UNSUPPORTED),
+    (dict(mode=9), nv.SPMM_ERR_INVALID),
+    (dict(rowptr=None), nv.SPMM_ERR_INVALID),
+    (dict(colind=None), nv.SPMM_ERR_INVALID),
+    (dict(m=2**31), nv.SPMM_ERR_UNSUPPORTED),
+    (dict(k=0), nv.SPMM_ERR_INVALID),
+])
+def test_plan_create_rejects(kw, status):
+    assert _create(**kw) == status
+    assert nv.spmm_last_error()
+
+
+def test_foreign_and_null_handles():
+    L = nv.lib()
+    bogus = ctypes.c_void_p(0x1234560)
+    assert L.spmm_execute(bogus, None, None, None, None) == nv.SPMM_ERR_STATE
+    assert L.spmm_plan_destroy(bogus) == nv.SPMM_ERR_STATE
+    assert L.spmm_plan_destroy(None) == nv.SPMM_ERR_STATE
+    assert L.spmm_plan_info_get(bogus, None) == nv.SPMM_ERR_STATE
+    assert L.spmm_sddmm(bogus, None, None, None, None) == nv.SPMM_ERR_STATE
+    assert L.spmm_execute_t(bogus, None, None, None, None) == nv.SPMM_ERR_STATE
+    assert L.spmm_transpose_build(bogus, None) == nv.SPMM_ERR_STATE
+    assert L.spmm_batch_run(bogus, None) == nv.SPMM_ERR_STATE
+    assert L.spmm_batch_destroy(bogus) == nv.SPMM_ERR_STATE
+
+
+def test_spmm_csr_noop_and_checks():
+    L = nv.lib()
+    # m == 0 or n == 0: no-op, no memory touched
+    assert L.spmm_csr(None, None, None, None, None, 0, 5, 4, 4, None) == nv.SPMM_OK
+    assert L.spmm_csr(None, None, None, None, None, 5, 5, 0, 1, None) == nv.SPMM_OK
+    assert L.spmm_csr(None, None, None, None, None, 5, 5, 4, 2, None) == nv.SPMM_ERR_INVALID
+    assert L.spmm_csr(None, None, None, None, None, -1, 5, 4, 4, None) == nv.SPMM_ERR_INVALID
+
+
+def test_config_struct_layout():
+    assert ctypes.sizeof(nv.spmm_config) == 20
+    assert ctypes.sizeof(nv.spmm_problem) == 5 * 8 + 5 * 8
