@@ -1,0 +1,337 @@
+// Backward kernels for L = <dC, A B> (not in the paper, whose Sec. 6 names
+// A^T products as future work):
+//   - the CSR of A^T, built once per structure by a stable LSD radix sort of
+//     (column index, entry position) pairs with 8-bit digits. Stability keeps
+//     the entries of each column in entry order, i.e. in increasing row of A,
+//     so the result is unique and equals a sequential counting sort;
+//   - the per-call gather AT_vals[q] = vals[perm[q]] (widened to float32);
+//   - SDDMM: dvals[p] = <dC[row(p), :], B[colind[p], :]>.
+// dB = A^T dC then runs through the forward kernels on the transposed CSR.
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spmmk {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortRounds = 32;                    // 64-item rounds per tile
+constexpr int kSortTile = kWave * kSortRounds;     // items per tile (one wavefront per tile)
+
+// Per-tile digit counts: hist[d * ntiles + t].
+__global__ __launch_bounds__(kWave) void k_radix_hist(const int* __restrict__ keys, int64_t n,
+                                                       int shift, int64_t ntiles,
+                                                       int* __restrict__ hist) {
+    __shared__ int cnt[kRadix];
+    const int64_t t = blockIdx.x;
+    for (int d = threadIdx.x; d < kRadix; d += kWave) cnt[d] = 0;
+    __syncthreads();
+    const int64_t base = t * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + r * kWave + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadix - 1)], 1);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kRadix; d += kWave) hist[(int64_t)d * ntiles + t] = cnt[d];
+}
+
+// Exclusive scan of `len` ints in place by one workgroup of 1024 threads:
+// each thread scans a contiguous chunk, chunk sums are scanned in LDS.
+__global__ __launch_bounds__(1024) void k_scan_single(int* __restrict__ a, int64_t len) {
+    __shared__ int sums[1024];
+    const int64_t per = (len + 1023) / 1024;
+    const int64_t lo = threadIdx.x * per;
+    const int64_t hi = lo + per < len ? lo + per : len;
+    int s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += a[i];
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+        const int v = threadIdx.x >= off ? sums[threadIdx.x - off] : 0;
+        __syncthreads();
+        sums[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = threadIdx.x ? sums[threadIdx.x - 1] : 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+// Stable scatter of one digit pass. One wavefront walks its tile in rounds of
+// 64 consecutive items; within a round, lanes holding the same digit find
+// each other with 8 ballots and take ranks in lane order, so item order is
+// kept within the tile; tiles are placed in order by the scanned counts.
+__global__ __launch_bounds__(kWave) void k_radix_scatter(const int* __restrict__ keys_in,
+                                                          const int* __restrict__ vals_in,
+                                                          int* __restrict__ keys_out,
+                                                          int* __restrict__ vals_out, int64_t n,
+                                                          int shift, int64_t ntiles,
+                                                          const int* __restrict__ offs) {
+    __shared__ int next[kRadix];
+    const int64_t t = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (int d = lane; d < kRadix; d += kWave) next[d] = offs[(int64_t)d * ntiles + t];
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = t * kSortTile;
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + r * kWave + lane;
+        const bool ok = i < n;
+        const int key = ok ? keys_in[i] : 0;
+        const int val = ok ? vals_in[i] : 0;
+        const int d = (key >> shift) & (kRadix - 1);
+        uint64_t match = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const uint64_t ones = __ballot(ok && ((d >> b) & 1));
+            match &= ((d >> b) & 1) ? ones : ~ones;
+        }
+        const int rank = __popcll(match & lt);
+        const int pos = ok ? next[d] + rank : 0;
+        __syncthreads();
+        if (ok) {
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+            // the highest lane of each digit group advances that digit's cursor
+            if ((match >> lane) == 1ull) next[d] = pos + 1;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota(int* __restrict__ a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = (int)i;
+}
+
+// AT_rowptr[c] = number of sorted keys below c, for c = 0..k.
+__global__ __launch_bounds__(kBlock) void k_lower_bounds(const int* __restrict__ sorted, int64_t n,
+                                                          int64_t k, int* __restrict__ out) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= k;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (sorted[mid] < c) lo = mid + 1; else hi = mid;
+        }
+        out[c] = (int)lo;
+    }
+}
+
+// AT_colind[q] = the row of A holding entry perm[q]: the last i with
+// rowptr[i] <= perm[q].
+__global__ __launch_bounds__(kBlock) void k_rows_of(const int* __restrict__ rowptr, int64_t m,
+                                                     const int* __restrict__ perm, int64_t n,
+                                                     int* __restrict__ out) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int p = perm[q];
+        int64_t lo = 0, hi = m;  // find largest i in [0, m) with rowptr[i] <= p
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (rowptr[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        out[q] = (int)lo;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_gather_widen(const typename S::T* __restrict__ vals,
+                                                          const int* __restrict__ perm, int64_t n,
+                                                          float* __restrict__ out) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        float v[1];
+        load_row<S, 1>(vals + perm[q], v);
+        __builtin_nontemporal_store(v[0], out + q);
+    }
+}
+
+static uint32_t grid_for(int64_t n, int64_t cap = 65536) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+hipError_t transpose_build(const int* rowptr, const int* colind, int64_t m, int64_t k,
+                           int64_t nnz, int* at_rowptr, int* at_colind, int* perm,
+                           int* tmp_keys0, int* tmp_keys1, int* tmp_vals1, int* hist,
+                           hipStream_t st) {
+    // keys: column indices; values: entry positions (perm ends up in `perm`)
+    hipError_t e = hipMemcpyAsync(tmp_keys0, colind, sizeof(int) * nnz, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(nnz)), dim3(kBlock), 0, st, perm, nnz);
+    int bits = 0;
+    while (bits < 31 && (int64_t(1) << bits) < k) ++bits;
+    const int passes = (bits + kRadixBits - 1) / kRadixBits;
+    const int64_t ntiles = (nnz + kSortTile - 1) / kSortTile;
+    int *kin = tmp_keys0, *kout = tmp_keys1, *vin = perm, *vout = tmp_vals1;
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = ps * kRadixBits;
+        hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)ntiles), dim3(kWave), 0, st, kin, nnz,
+                           shift, ntiles, hist);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, hist, ntiles * kRadix);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)ntiles), dim3(kWave), 0, st, kin, vin,
+                           kout, vout, nnz, shift, ntiles, hist);
+        int* tk = kin; kin = kout; kout = tk;
+        int* tv = vin; vin = vout; vout = tv;
+    }
+    if (vin != perm) {
+        e = hipMemcpyAsync(perm, vin, sizeof(int) * nnz, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_lower_bounds, dim3(grid_for(k + 1)), dim3(kBlock), 0, st, kin, nnz, k,
+                       at_rowptr);
+    hipLaunchKernelGGL(k_rows_of, dim3(grid_for(nnz)), dim3(kBlock), 0, st, rowptr, m, perm, nnz,
+                       at_colind);
+    return hipGetLastError();
+}
+
+int64_t transpose_hist_len(int64_t nnz) { return ((nnz + kSortTile - 1) / kSortTile) * kRadix; }
+
+hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int64_t n,
+                               float* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    switch (dtype) {
+    case 0: hipLaunchKernelGGL(k_gather_widen<F32>, dim3(grid_for(n)), dim3(kBlock), 0, st,
+                               static_cast<const float*>(vals), perm, n, out); break;
+    case 1: hipLaunchKernelGGL(k_gather_widen<BF16>, dim3(grid_for(n)), dim3(kBlock), 0, st,
+                               static_cast<const uint16_t*>(vals), perm, n, out); break;
+    case 2: hipLaunchKernelGGL(k_gather_widen<F16>, dim3(grid_for(n)), dim3(kBlock), 0, st,
+                               static_cast<const uint16_t*>(vals), perm, n, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ SDDMM
+//
+// Entries are split evenly: slot s (2^g_log2 lanes covering one column tile
+// of a row) takes entries [s E, (s+1) E), finds the row of its first entry
+// by binary search, and walks them in order, reloading its dC row chunk only
+// when the row changes. Per entry it gathers the B row chunk, forms VEC
+// partial products, loops over the column tiles, and reduces the slot's
+// lanes with a butterfly; lane 0 of the slot writes dvals[p]. The split is
+// independent of row lengths, so long rows cost no more than short ones.
+template <class S, int VEC, int U>
+__global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr,
+                                                   const int* __restrict__ colind,
+                                                   const float* __restrict__ dC,
+                                                   const typename S::T* __restrict__ B,
+                                                   float* __restrict__ dvals, int64_t m,
+                                                   int64_t nnz, int n, int64_t ld, int g_log2,
+                                                   int col_tiles, int E) {
+    const int G = 1 << g_log2;
+    const int g = threadIdx.x & (G - 1);
+    const int64_t slot = ((int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> g_log2;
+    const int64_t p0 = slot * E;
+    if (p0 >= nnz) return;  // whole slot leaves together (E and G fixed per slot)
+    const int64_t p1 = p0 + E < nnz ? p0 + E : nnz;
+    int64_t lo = 0, hi = m - 1;  // last row with rowptr[row] <= p0
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (rowptr[mid] <= p0) lo = mid; else hi = mid - 1;
+    }
+    int64_t row = lo;
+    int64_t row_end = rowptr[row + 1];
+    const int span = VEC << g_log2;
+    for (int64_t pb = p0; pb < p1; pb += U) {
+        float part[U];
+        int c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            part[u] = 0.f;
+            c[u] = pb + u < p1 ? __builtin_nontemporal_load(colind + pb + u) : 0;
+        }
+        for (int t = 0; t < col_tiles; ++t) {
+            const int col = t * span + g * VEC;
+            const bool col_ok = col < n;
+            float b[U][VEC];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (pb + u < p1 && col_ok) {
+                    load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
+                }
+            }
+            int64_t r = row, re = row_end;
+            float d[VEC];
+            bool have = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t p = pb + u;
+                if (p < p1) {
+                    bool moved = false;
+                    while (re <= p) { ++r; re = rowptr[r + 1]; moved = true; }
+                    if (!have || moved) {
+                        if (col_ok) load_f32<VEC>(dC + r * ld + col, d);
+                        else {
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e) d[e] = 0.f;
+                        }
+                        have = true;
+                    }
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) part[u] = fmaf(d[e], b[u][e], part[u]);
+                }
+            }
+            if (t == col_tiles - 1) { row = r; row_end = re; }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            for (int off = 1; off < G; off <<= 1) part[u] += __shfl_xor(part[u], off, kWave);
+            if (g == 0 && pb + u < p1) __builtin_nontemporal_store(part[u], dvals + pb + u);
+        }
+    }
+}
+
+template <class S, int VEC>
+static hipError_t sddmm_go(int unroll, int g_log2, int col_tiles, int E, const int* rowptr,
+                           const int* colind, const float* dC, const void* B, float* dvals,
+                           int64_t m, int64_t nnz, int64_t n, int64_t ld, hipStream_t st) {
+    const int64_t slots = (nnz + E - 1) / E;
+    const int64_t threads = slots << g_log2;
+    const uint32_t grid = (uint32_t)((threads + kBlock - 1) / kBlock);
+    const typename S::T* Bp = static_cast<const typename S::T*>(B);
+#define SDDMM_LAUNCH(UU)                                                                        \
+    hipLaunchKernelGGL((k_sddmm<S, VEC, UU>), dim3(grid), dim3(kBlock), 0, st, rowptr, colind, \
+                       dC, Bp, dvals, m, nnz, (int)n, ld, g_log2, col_tiles, E)
+    switch (unroll) {
+    case 1: SDDMM_LAUNCH(1); break;
+    case 2: SDDMM_LAUNCH(2); break;
+    case 4: SDDMM_LAUNCH(4); break;
+    case 8: SDDMM_LAUNCH(8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SDDMM_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_sddmm(int dtype, int vec, int unroll, int g_log2, int col_tiles, int E,
+                        const int* rowptr, const int* colind, const float* dC, const void* B,
+                        float* dvals, int64_t m, int64_t nnz, int64_t n, int64_t ld,
+                        hipStream_t st) {
+    if (nnz <= 0 || m <= 0) return hipSuccess;
+    if ((((nnz + E - 1) / E) << g_log2) >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+    switch (dtype) {
+    case 0:
+        if (vec == 4) return sddmm_go<F32, 4>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
+        return sddmm_go<F32, 1>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
+    case 1:
+        if (vec == 8) return sddmm_go<BF16, 8>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
+        return sddmm_go<BF16, 1>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
+    case 2:
+        if (vec == 8) return sddmm_go<F16, 8>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
+        return sddmm_go<F16, 1>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace spmmk
