@@ -17,7 +17,6 @@ this host's cores as a baseline.
 """
 import argparse
 import ctypes
-import glob
 import hashlib
 import json
 import os
@@ -31,10 +30,12 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
 
 
-def kernel_source_hash():
+def kernel_source_hash(files):
+    """Hash of the sources a kernel is built from (counters taken on another
+    version of them do not describe the current kernel)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1803_08601_amd", "csrc", "*"))):
-        h.update(open(p, "rb").read())
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_1803_08601_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -180,8 +181,10 @@ def main():
         rec = json.load(open(COUNTERS))
         key = f"{args.workload}-n{n}-{args.dtype}-{kernel}"
         r = rec.get(key)
-        if r and r.get("kernel_source_sha") == kernel_source_hash():
-            traffic = (r["fetch_kib"] + r["write_kib"]) * 1024.0 * r["copy_scale"]
+        if (r and r.get("kernel_source_sha") == kernel_source_hash(r["files"])
+                and r.get("config") in (None, info.config.as_dict())):
+            traffic = round(r["fetch_kib"] * 1024.0 * r["fetch_scale"]
+                            + r["write_kib"] * 1024.0 * r["write_scale"])
 
     out = {
         "metric": "SpMM GFLOP/s (2*nnz*n/t)",

@@ -54,7 +54,7 @@ static int ilog2_ceil(int64_t x) {
 
 // Lanes that cover one B row (capped at a wavefront; wider rows use column
 // tiles) and the resulting number of column tiles.
-static void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles) {
+void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles) {
     int64_t lanes = (n + vec - 1) / vec;
     if (lanes < 1) lanes = 1;
     if (lanes > spmmk::kWaveSize) lanes = spmmk::kWaveSize;
@@ -76,7 +76,7 @@ spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec) {
     return s;
 }
 
-static bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
+bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
 
 static size_t lds_limit() {
     static size_t lim = 0;

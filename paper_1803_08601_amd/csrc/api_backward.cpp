@@ -1,0 +1,129 @@
+// C ABI of the backward pass: transpose build, dB = A^T dC and SDDMM.
+
+#include <hip/hip_runtime.h>
+
+#include "plan.hpp"
+
+using namespace spmmh;
+
+namespace {
+
+// SDDMM entries per slot: enough consecutive entries to reuse the dC row
+// chunk across short rows, few enough to keep every slot busy.
+constexpr int kSddmmEntries = 16;
+constexpr int kSddmmUnroll = 4;
+
+}  // namespace
+
+extern "C" {
+
+int spmm_transpose_build(spmm_plan_t plan, void* stream) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (plan->tplan) return SPMM_OK;  // once per structure
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    spmm_plan_s& p = *plan;
+    Transpose& tr = p.tr;
+    int *k0 = nullptr, *k1 = nullptr, *v1 = nullptr, *hist = nullptr;
+    auto free_tmp = [&]() {
+        if (k0) (void)hipFree(k0);
+        if (k1) (void)hipFree(k1);
+        if (v1) (void)hipFree(v1);
+        if (hist) (void)hipFree(hist);
+    };
+    auto free_tr = [&]() {
+        if (tr.at_rowptr) (void)hipFree(tr.at_rowptr);
+        if (tr.at_colind) (void)hipFree(tr.at_colind);
+        if (tr.perm) (void)hipFree(tr.perm);
+        if (tr.at_vals) (void)hipFree(tr.at_vals);
+        tr = Transpose{};
+    };
+    hipError_t e = hipMalloc(&tr.at_rowptr, sizeof(int) * (p.k + 1));
+    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&tr.at_colind, sizeof(int) * p.nnz);
+    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&tr.perm, sizeof(int) * p.nnz);
+    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&tr.at_vals, sizeof(float) * p.nnz);
+    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&k0, sizeof(int) * p.nnz);
+    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&k1, sizeof(int) * p.nnz);
+    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&v1, sizeof(int) * p.nnz);
+    if (e == hipSuccess && p.nnz > 0)
+        e = hipMalloc(&hist, sizeof(int) * spmmk::transpose_hist_len(p.nnz));
+    if (e == hipSuccess) {
+        if (p.nnz > 0)
+            e = spmmk::transpose_build(p.rowptr, p.colind, p.m, p.k, p.nnz, tr.at_rowptr,
+                                       tr.at_colind, tr.perm, k0, k1, v1, hist, st);
+        else
+            e = hipMemsetAsync(tr.at_rowptr, 0, sizeof(int) * (p.k + 1), st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    free_tmp();
+    if (e != hipSuccess) {
+        free_tr();
+        return hip_fail(e, "transpose build");
+    }
+    // The product with A^T runs in float32 (values are widened at gather).
+    const int mode = p.mode >= 0 ? p.mode : SPMM_MODE_PAPER;
+    spmm_plan_s* tp = nullptr;
+    int rc = create_plan(&tp, tr.at_rowptr, tr.at_colind, p.k, p.m, p.nnz, p.n, p.ld, SPMM_F32,
+                         mode, nullptr, st, false);
+    if (rc != SPMM_OK) {
+        free_tr();
+        return rc;
+    }
+    p.tplan = tp;
+    return SPMM_OK;
+}
+
+int spmm_transpose_get(spmm_plan_t plan, int32_t* AT_rowptr, int32_t* AT_colind, int32_t* perm,
+                       void* stream) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (!plan->tplan) return fail(SPMM_ERR_STATE, "spmm_transpose_build has not run");
+    if (!AT_rowptr || (plan->nnz > 0 && (!AT_colind || !perm)))
+        return fail(SPMM_ERR_INVALID, "output pointer is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const auto d2d = hipMemcpyDeviceToDevice;
+    SPMM_HIP(hipMemcpyAsync(AT_rowptr, plan->tr.at_rowptr, sizeof(int) * (plan->k + 1), d2d, st));
+    if (plan->nnz > 0) {
+        SPMM_HIP(hipMemcpyAsync(AT_colind, plan->tr.at_colind, sizeof(int) * plan->nnz, d2d, st));
+        SPMM_HIP(hipMemcpyAsync(perm, plan->tr.perm, sizeof(int) * plan->nnz, d2d, st));
+    }
+    return SPMM_OK;
+}
+
+int spmm_execute_t(spmm_plan_t plan, const void* A_vals, const float* dC, float* dB,
+                   void* stream) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (!plan->tplan) return fail(SPMM_ERR_STATE, "spmm_transpose_build has not run");
+    if (plan->k == 0 || plan->n == 0) return SPMM_OK;
+    if (!dB) return fail(SPMM_ERR_INVALID, "dB is NULL");
+    if (plan->nnz > 0 && (!A_vals || !dC)) return fail(SPMM_ERR_INVALID, "A_vals or dC is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (plan->nnz > 0) {
+        hipError_t e = spmmk::launch_gather_widen(plan->dtype, A_vals, plan->tr.perm, plan->nnz,
+                                                  static_cast<float*>(plan->tr.at_vals), st);
+        if (e != hipSuccess) return hip_fail(e, "value gather launch");
+    }
+    const spmm_plan_s& tp = *plan->tplan;
+    return forward(tp, tp.rowptr, tp.colind, plan->tr.at_vals, dC, dB, st);
+}
+
+int spmm_sddmm(spmm_plan_t plan, const float* dC, const void* B, float* dvals, void* stream) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (plan->nnz == 0 || plan->m == 0) return SPMM_OK;
+    if (!dvals) return fail(SPMM_ERR_INVALID, "dvals is NULL");
+    if (plan->n > 0 && (!dC || !B)) return fail(SPMM_ERR_INVALID, "dC or B is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (plan->n == 0) {
+        SPMM_HIP(hipMemsetAsync(dvals, 0, sizeof(float) * plan->nnz, st));
+        return SPMM_OK;
+    }
+    int vec = plan->cfg.vec;
+    if (vec != 1 && (!aligned16(dC) || !aligned16(B))) vec = 1;
+    int g_log2, col_tiles;
+    slot_geometry(plan->n, vec, &g_log2, &col_tiles);
+    hipError_t e = spmmk::launch_sddmm(plan->dtype, vec, kSddmmUnroll, g_log2, col_tiles,
+                                       kSddmmEntries, plan->rowptr, plan->colind, dC, B, dvals,
+                                       plan->m, plan->nnz, plan->n, plan->ld, st);
+    if (e != hipSuccess) return hip_fail(e, "SDDMM launch");
+    return SPMM_OK;
+}
+
+}  // extern "C"

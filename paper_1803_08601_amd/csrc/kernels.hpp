@@ -47,4 +47,22 @@ hipError_t launch_check_cols(const int* colind, int64_t nnz, int64_t k, int* fla
 
 size_t merge_lds_bytes(int dtype, const Shape& s);
 
+// CSR of A^T by a stable radix sort of (column, entry) pairs. Scratch:
+// tmp_keys0/tmp_keys1/tmp_vals1 of nnz ints, hist of transpose_hist_len(nnz).
+hipError_t transpose_build(const int* rowptr, const int* colind, int64_t m, int64_t k,
+                           int64_t nnz, int* at_rowptr, int* at_colind, int* perm,
+                           int* tmp_keys0, int* tmp_keys1, int* tmp_vals1, int* hist,
+                           hipStream_t st);
+int64_t transpose_hist_len(int64_t nnz);
+
+// out[q] = widen(vals[perm[q]]) for q < n.
+hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int64_t n,
+                               float* out, hipStream_t st);
+
+// dvals[p] = <dC[row(p), :n], B[colind[p], :n]>, E entries per slot.
+hipError_t launch_sddmm(int dtype, int vec, int unroll, int g_log2, int col_tiles, int E,
+                        const int* rowptr, const int* colind, const float* dC, const void* B,
+                        float* dvals, int64_t m, int64_t nnz, int64_t n, int64_t ld,
+                        hipStream_t st);
+
 }  // namespace spmmk

@@ -4,10 +4,6 @@
 using namespace spmmh;
 
 extern "C" {
-int spmm_transpose_build(spmm_plan_t, void*) { return fail(SPMM_ERR_UNSUPPORTED, "not built yet"); }
-int spmm_transpose_get(spmm_plan_t, int32_t*, int32_t*, int32_t*, void*) { return fail(SPMM_ERR_UNSUPPORTED, "not built yet"); }
-int spmm_execute_t(spmm_plan_t, const void*, const float*, float*, void*) { return fail(SPMM_ERR_UNSUPPORTED, "not built yet"); }
-int spmm_sddmm(spmm_plan_t, const float*, const void*, float*, void*) { return fail(SPMM_ERR_UNSUPPORTED, "not built yet"); }
 int spmm_batch_plan(spmm_batch_t*, const spmm_problem*, int64_t, int32_t, int32_t, void*) { return fail(SPMM_ERR_UNSUPPORTED, "not built yet"); }
 int spmm_batch_run(spmm_batch_t, void*) { return fail(SPMM_ERR_UNSUPPORTED, "not built yet"); }
 int spmm_batch_run_direct(spmm_batch_t, void*) { return fail(SPMM_ERR_UNSUPPORTED, "not built yet"); }

@@ -57,6 +57,8 @@ struct spmm_plan_s {
 namespace spmmh {
 
 bool plan_alive(const spmm_plan_s* p);
+bool aligned16(const void* ptr);
+void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles);
 int elem_bytes(int dtype);
 int vec16(int dtype);
 spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec);
