@@ -192,29 +192,35 @@ static int check_config(const spmm_plan_s& p, spmm_config& c) {
 struct TuneKey {
     int device;
     int64_t m, k, nnz, n, ld, maxrow, longrows;
-    int dtype;
+    int dtype, unroll;
     bool operator<(const TuneKey& o) const {
-        return std::tie(device, m, k, nnz, n, ld, maxrow, longrows, dtype) <
-               std::tie(o.device, o.m, o.k, o.nnz, o.n, o.ld, o.maxrow, o.longrows, o.dtype);
+        return std::tie(device, m, k, nnz, n, ld, maxrow, longrows, dtype, unroll) <
+               std::tie(o.device, o.m, o.k, o.nnz, o.n, o.ld, o.maxrow, o.longrows, o.dtype,
+                        o.unroll);
     }
 };
 static std::map<TuneKey, std::pair<spmm_config, double>> g_tuned;
 
-static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p) {
+static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_unroll) {
     std::vector<spmm_config> out;
     const int v16 = vec16(p.dtype);
     const int vec = (p.n % v16 == 0 && p.ld % v16 == 0) ? v16 : 1;
     int g_log2, tiles;
     slot_geometry(p.n, vec, &g_log2, &tiles);
+    std::vector<int> unrolls = {2, 4, 8};
+    if (fixed_unroll) unrolls = {fixed_unroll};
     for (int lpr = 1 << g_log2; lpr <= spmmk::kWaveSize; lpr *= 2)
-        for (int u : {2, 4, 8}) out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024});
+        for (int u : unrolls) out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024});
     for (int W : {512, 1024, 2048, 4096})
-        for (int u : {2, 4, 8}) out.push_back({SPMM_KERNEL_MERGE, vec, 1 << g_log2, u, W});
+        for (int u : unrolls) out.push_back({SPMM_KERNEL_MERGE, vec, 1 << g_log2, u, W});
     return out;
 }
 
-static int autotune(spmm_plan_s& p, hipStream_t st) {
-    const TuneKey key{p.device, p.m, p.k, p.nnz, p.n, p.ld, p.max_row_len, p.long_rows, p.dtype};
+static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
+    const int fixed_unroll = opts ? opts->fixed_unroll : 0;
+    const bool own = opts && opts->C && (p.nnz == 0 || (opts->vals && opts->B));
+    const TuneKey key{p.device, p.m, p.k, p.nnz, p.n, p.ld, p.max_row_len, p.long_rows, p.dtype,
+                      fixed_unroll};
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tuned.find(key);
@@ -225,12 +231,15 @@ static int autotune(spmm_plan_s& p, hipStream_t st) {
         }
     }
     if (p.m == 0 || p.n == 0) {
-        p.cfg = spmm_config{p.paper_choice, 0, 0, 0, 0};
+        p.cfg = spmm_config{p.paper_choice, 0, 0, fixed_unroll, 0};
         return check_config(p, p.cfg);
     }
     const int eb = elem_bytes(p.dtype);
     void *vals = nullptr, *B = nullptr;
     float* C = nullptr;
+    const void* use_vals = own ? opts->vals : nullptr;
+    const void* use_B = own ? opts->B : nullptr;
+    float* use_C = own ? opts->C : nullptr;
     MergeWs ws;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SPMM_OK;
@@ -251,17 +260,22 @@ static int autotune(spmm_plan_s& p, hipStream_t st) {
             return rc;                                  \
         }                                               \
     } while (0)
-    if (p.nnz > 0) TUNE_HIP(hipMalloc(&vals, (size_t)eb * p.nnz));
-    if (p.k > 0) TUNE_HIP(hipMalloc(&B, (size_t)eb * p.k * p.ld));
-    TUNE_HIP(hipMalloc(&C, sizeof(float) * p.m * p.ld));
-    if (vals) TUNE_HIP(hipMemsetAsync(vals, 0x3c, (size_t)eb * p.nnz, st));
-    if (B) TUNE_HIP(hipMemsetAsync(B, 0x3c, (size_t)eb * p.k * p.ld, st));
+    if (!own) {
+        if (p.nnz > 0) TUNE_HIP(hipMalloc(&vals, (size_t)eb * p.nnz));
+        if (p.k > 0) TUNE_HIP(hipMalloc(&B, (size_t)eb * p.k * p.ld));
+        TUNE_HIP(hipMalloc(&C, sizeof(float) * p.m * p.ld));
+        if (vals) TUNE_HIP(hipMemsetAsync(vals, 0x3c, (size_t)eb * p.nnz, st));
+        if (B) TUNE_HIP(hipMemsetAsync(B, 0x3c, (size_t)eb * p.k * p.ld, st));
+        use_vals = vals;
+        use_B = B;
+        use_C = C;
+    }
     TUNE_HIP(hipEventCreate(&e0));
     TUNE_HIP(hipEventCreate(&e1));
 
     double best = 1e30;
     spmm_config best_cfg{};
-    for (spmm_config c : tune_candidates(p)) {
+    for (spmm_config c : tune_candidates(p, fixed_unroll)) {
         spmm_plan_s q = p;  // shallow copy: never destroyed
         q.ws = MergeWs{};
         if (check_config(q, c) != SPMM_OK) continue;
@@ -274,7 +288,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st) {
         std::vector<float> times;
         for (int rep = 0; rep < 4; ++rep) {
             TUNE_HIP(hipEventRecord(e0, st));
-            rc = forward(q, q.rowptr, q.colind, vals, B, C, st);
+            rc = forward(q, q.rowptr, q.colind, use_vals, use_B, use_C, st);
             if (rc != SPMM_OK) { cleanup(); return rc; }
             TUNE_HIP(hipEventRecord(e1, st));
             TUNE_HIP(hipEventSynchronize(e1));
@@ -347,7 +361,8 @@ void destroy_plan(spmm_plan_s* p) {
 
 int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, int64_t m,
                 int64_t k, int64_t nnz, int64_t n, int64_t ld, int32_t dtype, int32_t mode,
-                const spmm_config* forced, hipStream_t st, bool register_plan) {
+                const spmm_config* forced, hipStream_t st, bool register_plan,
+                const TuneOpts* opts) {
     if (!out) return fail(SPMM_ERR_INVALID, "out_plan is NULL");
     *out = nullptr;
     int rc = check_dims(m, k, nnz, n, ld);
@@ -377,12 +392,12 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
             p->cfg = *forced;
             rc = check_config(*p, p->cfg);
         } else if (mode == SPMM_MODE_AUTOTUNE) {
-            rc = autotune(*p, st);
+            rc = autotune(*p, st, opts);
         } else {
             const int kern = mode == SPMM_MODE_PAPER    ? p->paper_choice
                              : mode == SPMM_MODE_MERGE ? SPMM_KERNEL_MERGE
                                                         : SPMM_KERNEL_ROWSPLIT;
-            p->cfg = spmm_config{kern, 0, 0, 0, 0};
+            p->cfg = spmm_config{kern, 0, 0, opts ? opts->fixed_unroll : 0, 0};
             rc = check_config(*p, p->cfg);
         }
     }

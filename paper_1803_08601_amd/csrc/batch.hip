@@ -1,0 +1,132 @@
+// Batched SpMM: many independent products C_b = A_b B_b in one persistent
+// kernel (not in the paper; it applies the paper's two kernels per problem).
+//
+// The host lays out a work list: every problem contributes its tiles - a
+// workgroup's rows for row-split problems, a merge piece for merge-based
+// problems - times its column tiles, problems with the costliest tiles first.
+// A grid of exactly as many workgroups as fit on the GPU at once takes tiles
+// from one atomic counter until the list is exhausted; each tile runs the same
+// device function as the single-product kernels, with that problem's shape.
+// The counter only grows, so every workgroup reaches the end of the list and
+// exits. A second launch adds the carry-outs of all merge-based problems
+// (Phase 3), and a one-thread kernel re-arms the counter for the next run.
+
+#include "batch.hpp"
+#include "tiles.hpp"
+
+namespace spmmk {
+
+__global__ void k_batch_reset(unsigned long long* counter) { *counter = 0ull; }
+
+template <class S, int U>
+__global__ __launch_bounds__(kBlock) void k_batch(const BatchProb* __restrict__ probs,
+                                                   const int64_t* __restrict__ item_off,
+                                                   int nprob, int64_t total,
+                                                   unsigned long long* __restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t it = s_item;
+        __syncthreads();  // everyone has read s_item before it is overwritten
+        if (it >= total) break;
+        int lo = 0, hi = nprob - 1;  // last problem whose first item is <= it
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (item_off[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const BatchProb& p = probs[lo];
+        const int64_t local = it - item_off[lo];
+        const int coltile = (int)(local % p.col_tiles);
+        const int64_t idx = local / p.col_tiles;
+        const typename S::T* vals = static_cast<const typename S::T*>(p.vals);
+        const typename S::T* B = static_cast<const typename S::T*>(p.B);
+        if (p.kernel == 0) {
+            if (p.vec == 1)
+                rowsplit_block<S, 1, U>(p.rowptr, p.colind, vals, B, p.C, p.m, p.n, p.ld,
+                                        p.g_log2, p.ts_log2, idx, coltile);
+            else
+                rowsplit_block<S, S::kVec16, U>(p.rowptr, p.colind, vals, B, p.C, p.m, p.n, p.ld,
+                                                p.g_log2, p.ts_log2, idx, coltile);
+        } else {
+            if (p.vec == 1)
+                merge_tile<S, 1, U>(p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n, p.ld,
+                                    p.g_log2, p.coords, p.W, p.carry_vals, p.carry_rows,
+                                    (int)idx, coltile, smem);
+            else
+                merge_tile<S, S::kVec16, U>(p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n,
+                                            p.ld, p.g_log2, p.coords, p.W, p.carry_vals,
+                                            p.carry_rows, (int)idx, coltile, smem);
+        }
+        __syncthreads();  // LDS is reused by the next tile
+    }
+}
+
+// Phase 3 of every merge-based problem: piece g of the concatenated piece
+// list belongs to the last merge problem whose first piece is <= g.
+__global__ __launch_bounds__(kWave) void k_batch_fixup(const BatchProb* __restrict__ probs,
+                                                        const int* __restrict__ merge_ids,
+                                                        const int64_t* __restrict__ piece_off,
+                                                        int nmerge) {
+    const int64_t gp = blockIdx.x;
+    int lo = 0, hi = nmerge - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (piece_off[mid] <= gp) lo = mid; else hi = mid - 1;
+    }
+    const BatchProb& p = probs[merge_ids[lo]];
+    merge_fixup_piece(p.C, p.ld, p.n, p.carry_vals, p.carry_rows, p.P, gp - piece_off[lo]);
+}
+
+template <class S, int U>
+static const void* batch_kernel_ptr() {
+    return reinterpret_cast<const void*>(&k_batch<S, U>);
+}
+
+static const void* batch_fn(int dtype) {
+    switch (dtype) {
+    case 0: return batch_kernel_ptr<F32, kBatchUnroll>();
+    case 1: return batch_kernel_ptr<BF16, kBatchUnroll>();
+    case 2: return batch_kernel_ptr<F16, kBatchUnroll>();
+    default: return nullptr;
+    }
+}
+
+hipError_t batch_grid(int dtype, size_t lds, int* grid) {
+    const void* fn = batch_fn(dtype);
+    if (!fn) return hipErrorInvalidValue;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    *grid = cus * per_cu;
+    return hipSuccess;
+}
+
+hipError_t launch_batch(int dtype, int grid, size_t lds, const BatchProb* probs,
+                        const int64_t* item_off, int nprob, int64_t total,
+                        unsigned long long* counter, const int* merge_ids,
+                        const int64_t* piece_off, int nmerge, int64_t total_pieces,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, counter);
+    if (total > 0) {
+        switch (dtype) {
+        case 0: hipLaunchKernelGGL((k_batch<F32, kBatchUnroll>), dim3(grid), dim3(kBlock), lds, st,
+                                   probs, item_off, nprob, total, counter); break;
+        case 1: hipLaunchKernelGGL((k_batch<BF16, kBatchUnroll>), dim3(grid), dim3(kBlock), lds, st,
+                                   probs, item_off, nprob, total, counter); break;
+        case 2: hipLaunchKernelGGL((k_batch<F16, kBatchUnroll>), dim3(grid), dim3(kBlock), lds, st,
+                                   probs, item_off, nprob, total, counter); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (nmerge > 0 && total_pieces > 0)
+        hipLaunchKernelGGL(k_batch_fixup, dim3((uint32_t)total_pieces), dim3(kWave), 0, st, probs,
+                           merge_ids, piece_off, nmerge);
+    return hipGetLastError();
+}
+
+}  // namespace spmmk

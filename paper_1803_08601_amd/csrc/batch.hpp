@@ -1,0 +1,45 @@
+// Work description of the batched persistent kernel (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spmmk {
+
+// Unroll of the batched kernel: one instantiation keeps its register use
+// (and so its occupancy) independent of the mix of problems.
+constexpr int kBatchUnroll = 4;
+
+struct BatchProb {
+    const int* rowptr;
+    const int* colind;
+    const void* vals;
+    const void* B;
+    float* C;
+    int64_t m;
+    int64_t ld;
+    int n;
+    int kernel;   // 0 row split, 1 merge-based
+    int vec;
+    int g_log2;
+    int ts_log2;
+    int W;
+    int col_tiles;
+    int pad;
+    int64_t items;  // tiles of this problem (including column tiles)
+    const int* coords;
+    float* carry_vals;
+    int* carry_rows;
+    int64_t P;
+};
+
+// Workgroups of the persistent kernel that fit on the device at once.
+hipError_t batch_grid(int dtype, size_t lds, int* grid);
+
+hipError_t launch_batch(int dtype, int grid, size_t lds, const BatchProb* probs,
+                        const int64_t* item_off, int nprob, int64_t total,
+                        unsigned long long* counter, const int* merge_ids,
+                        const int64_t* piece_off, int nmerge, int64_t total_pieces,
+                        hipStream_t st);
+
+}  // namespace spmmk

@@ -1,37 +1,7 @@
-// Merge-based SpMM (paper Sec. 4.2, Algorithm 1) for gfx950.
-//
-// Phase 1 (PARTITIONSPMM): the merge of the row ends a[i] = rowptr[i+1] with
-// the entry indices b[j] = j is cut into pieces of W items (rows + entries)
-// by a 2-D binary search on the diagonals d_p = min(p W, m + nnz) (the merge
-// path of Sec. 4). At state (i, j) the next item is the end of row i when
-// a[i] <= j, otherwise entry j, which belongs to row i. Coordinates depend
-// only on A's structure, so a plan computes them once.
-//
-// Phase 2 (one workgroup per piece): the piece's row ends, column indices and
-// values are staged in LDS with coalesced loads (GLOBALTOSHARED). The piece
-// is split again, evenly, among the workgroup's slots (2^g_log2 lanes
-// covering one B row of the column tile) by the same diagonal search on the
-// LDS copy. Each slot walks its items in merge order: for an entry it
-// gathers the B row (U gathers in flight) and accumulates value * row; for a
-// row end it emits the running sum. A row whose entries all lie inside the
-// slot is written straight to C. The first row a slot finishes may have
-// started in earlier slots: it goes through LDS and is combined with the
-// carry-outs of those slots in slot order (the segmented reduction of
-// REDUCETOGLOBALSPMM). The sum for the row still open at the end of the piece
-// is the piece's carry-out (row id plus n floats).
-//
-// Phase 3 (FIXCARRYOUT): rows that cross piece boundaries receive the
-// carry-outs of the pieces before the one that finished them, added in piece
-// order by a separate pass, since workgroups cannot wait for each other.
-//
-// Every row is written exactly once by Phase 2 and updated at most once by
-// Phase 3; all sums run in an order fixed by (W, slot width), so results are
-// deterministic for a plan.
+// Merge-based SpMM kernels (paper Sec. 4.2, Algorithm 1): Phase 1 partition,
+// Phase 2 (tile function in tiles.hpp), Phase 3 fix-up; plus CSR statistics.
 
-#include <limits.h>
-
-#include "common.hpp"
-#include "kernels.hpp"
+#include "tiles.hpp"
 
 namespace spmmk {
 
@@ -65,169 +35,15 @@ __global__ __launch_bounds__(kBlock) void k_merge(const int* __restrict__ rowptr
                                                    int W, float* __restrict__ carry_vals,
                                                    int* __restrict__ carry_rows) {
     extern __shared__ __align__(16) unsigned char smem[];
-    float* s_head = reinterpret_cast<float*>(smem);     // [kBlock * VEC] first finished row per slot
-    float* s_carry = s_head + kBlock * VEC;              // [kBlock * VEC] open row per slot
-    float* s_val = s_carry + kBlock * VEC;               // [W]
-    int* s_col = reinterpret_cast<int*>(s_val + W);      // [W]
-    int* s_rowend = s_col + W;                           // [W] local row ends
-    int* s_head_row = s_rowend + W;                      // [kBlock]
-    int* s_carry_row = s_head_row + kBlock;              // [kBlock]
-
-    const int tile = (int)xcd_remap(blockIdx.x, gridDim.x);
-    const int i0 = coords[2 * tile], j0 = coords[2 * tile + 1];
-    const int i1 = coords[2 * tile + 2], j1 = coords[2 * tile + 3];
-    const int nr = i1 - i0, nj = j1 - j0;
-
-    for (int t = threadIdx.x; t < nr; t += kBlock)
-        s_rowend[t] = __builtin_nontemporal_load(rowptr + i0 + 1 + t) - j0;
-    for (int t = threadIdx.x; t < nj; t += kBlock) {
-        s_col[t] = __builtin_nontemporal_load(colind + j0 + t);
-        s_val[t] = load_elem(vals + j0 + t, S{});
-    }
-    const int G = 1 << g_log2;
-    const int NS = kBlock >> g_log2;
-    const int slot = threadIdx.x >> g_log2;
-    const int g = threadIdx.x & (G - 1);
-    if (g == 0) s_head_row[slot] = -1;
-    __syncthreads();
-
-    const int col = blockIdx.y * (VEC << g_log2) + g * VEC;
-    const bool col_ok = col < n;
-    const int items = nr + nj;
-    const int ips = (items + NS - 1) / NS;
-    const int d0 = min(slot * ips, items), d1 = min(d0 + ips, items);
-    auto search = [&](int d) {
-        int lo = max(0, d - nj), hi = min(d, nr);
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_rowend[mid] + mid < d)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        return lo;
-    };
-    const int rs = search(d0), js = d0 - rs;
-    const int re = search(d1), je = d1 - re;
-
-    float acc[VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
-    int r = rs;
-    int rend = r < nr ? s_rowend[r] : INT_MAX;
-    auto emit = [&]() {
-        if (r == rs) {
-            store_f32<VEC>(s_head + threadIdx.x * VEC, acc);
-            if (g == 0) s_head_row[slot] = r;
-        } else if (col_ok) {
-            store_out<VEC>(C + (int64_t)(i0 + r) * ld + col, acc);
-        }
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
-        ++r;
-        rend = r < nr ? s_rowend[r] : INT_MAX;
-    };
-
-    for (int jb = js; jb < je; jb += U) {
-        int c[U];
-        float v[U];
-        float b[U][VEC];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = jb + u < je;
-            c[u] = ok ? s_col[jb + u] : 0;
-            v[u] = ok ? s_val[jb + u] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (jb + u < je && col_ok) {
-                load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
-            } else {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = jb + u;
-            if (j < je) {
-                while (rend <= j) emit();
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v[u], b[u][e], acc[e]);
-            }
-        }
-    }
-    while (r < re) emit();
-    store_f32<VEC>(s_carry + threadIdx.x * VEC, acc);
-    if (g == 0) s_carry_row[slot] = re;
-    __syncthreads();
-
-    // First finished row of each slot: add the carry-outs of the earlier
-    // slots that ended inside the same row, in slot order.
-    const int h = s_head_row[slot];
-    if (h >= 0 && col_ok) {
-        int s0 = slot;
-        while (s0 > 0 && s_carry_row[s0 - 1] == h) --s0;
-        float tot[VEC];
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) tot[e] = 0.f;
-        for (int q = s0; q < slot; ++q) {
-            float t[VEC];
-            load_f32<VEC>(s_carry + (q * G + g) * VEC, t);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) tot[e] += t[e];
-        }
-        float hv[VEC];
-        load_f32<VEC>(s_head + threadIdx.x * VEC, hv);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) tot[e] += hv[e];
-        store_out<VEC>(C + (int64_t)(i0 + h) * ld + col, tot);
-    }
-
-    // Carry-out of the piece: the row open at its end (row i1), if the piece
-    // holds any of its entries.
-    if (slot == NS - 1) {
-        bool open = false;
-        if (i1 < m) {
-            const int start_local = nr > 0 ? s_rowend[nr - 1] : rowptr[i0] - j0;
-            open = nj > start_local;
-        }
-        if (open && col_ok) {
-            int s0 = NS - 1;
-            while (s0 > 0 && s_carry_row[s0 - 1] == nr) --s0;
-            float tot[VEC];
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) tot[e] = 0.f;
-            for (int q = s0; q < NS; ++q) {
-                float t[VEC];
-                load_f32<VEC>(s_carry + (q * G + g) * VEC, t);
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) tot[e] += t[e];
-            }
-            store_f32<VEC>(carry_vals + (int64_t)tile * n + col, tot);
-        }
-        if (g == 0 && blockIdx.y == 0) carry_rows[tile] = open ? i1 : -1;
-    }
+    merge_tile<S, VEC, U>(rowptr, colind, vals, B, C, m, n, ld, g_log2, coords, W, carry_vals,
+                          carry_rows, (int)xcd_remap(blockIdx.x, gridDim.x), blockIdx.y, smem);
 }
 
-// Phase 3: one wavefront per piece; the first piece of every run of pieces
-// that carry into the same row adds the run's carry-outs (in piece order) to
-// that row of C.
 __global__ __launch_bounds__(kWave) void k_merge_fixup(float* __restrict__ C, int64_t ld, int n,
                                                         const float* __restrict__ carry_vals,
                                                         const int* __restrict__ carry_rows,
                                                         int64_t P) {
-    const int64_t p = blockIdx.x;
-    const int r = carry_rows[p];
-    if (r < 0) return;
-    if (p > 0 && carry_rows[p - 1] == r) return;
-    int64_t q_end = p + 1;
-    while (q_end < P && carry_rows[q_end] == r) ++q_end;
-    for (int c = threadIdx.x; c < n; c += kWave) {
-        float s = 0.f;
-        for (int64_t q = p; q < q_end; ++q) s += carry_vals[q * n + c];
-        C[(int64_t)r * ld + c] += s;
-    }
+    merge_fixup_piece(C, ld, n, carry_vals, carry_rows, P, blockIdx.x);
 }
 
 size_t merge_lds_bytes(int dtype, const Shape& s) {

@@ -65,9 +65,19 @@ spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec);
 int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const void* vals,
             const void* B, float* C, hipStream_t st, hipEvent_t ev_before = nullptr,
             hipEvent_t ev_after = nullptr);
+// Options of plan creation used inside the library: a fixed unroll for every
+// candidate, and buffers of the caller to time candidates on (else scratch).
+struct TuneOpts {
+    int fixed_unroll = 0;
+    const void* vals = nullptr;
+    const void* B = nullptr;
+    float* C = nullptr;
+};
+
 int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, int64_t m,
                 int64_t k, int64_t nnz, int64_t n, int64_t ld, int32_t dtype, int32_t mode,
-                const spmm_config* forced, hipStream_t st, bool register_plan);
+                const spmm_config* forced, hipStream_t st, bool register_plan,
+                const TuneOpts* opts = nullptr);
 void destroy_plan(spmm_plan_s* p);
 
 }  // namespace spmmh

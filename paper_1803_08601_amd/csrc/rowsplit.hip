@@ -1,33 +1,6 @@
-// Row-split SpMM (paper Sec. 4.1, Fig. 3) for gfx950 wavefronts.
-//
-// The paper gives each row of A to one 32-lane warp whose lanes span 32
-// columns of B: every lane loads one (column index, value) pair of the row,
-// the pairs are broadcast across the warp with shuffles, and for each pair
-// the whole warp reads one row of B with a coalesced access, so B and C are
-// both touched row-major.
-//
-// On a 64-lane wavefront the same pattern is kept but the lane groups are
-// sized for the actual n:
-//   slot  = 2^g_log2 lanes that together cover vec * 2^g_log2 consecutive
-//           columns of one B row (16-byte accesses when vec is the 16-byte
-//           width), so one B row is a single coalesced request per slot;
-//   team  = 2^ts_log2 slots that own one row of A. The slots of a team walk
-//           disjoint entries of the row (entry t goes to slot t mod team
-//           slots), so short rows still fill the wavefront ("thread per
-//           row" granularity of Sec. 4.1 when the team is one slot) and
-//           long rows get several B rows in flight per step.
-// A team loads up to its lane count of (column, value) pairs with one
-// coalesced access per lane and broadcasts them to its slots with ds_bpermute
-// (the wave64 form of the paper's shuffle broadcast). Each slot keeps U
-// B-row gathers in flight before it accumulates them (the ILP of Table 1).
-// At the end of the row the team's slots are combined by a butterfly of
-// lane exchanges and the first slot writes the C row once.
-//
-// The result is fully determined by the launch shape: the accumulation order
-// inside a slot and the butterfly order are fixed.
+// Row-split SpMM kernel (paper Sec. 4.1); the tile function lives in tiles.hpp.
 
-#include "common.hpp"
-#include "kernels.hpp"
+#include "tiles.hpp"
 
 namespace spmmk {
 
@@ -38,75 +11,11 @@ __global__ __launch_bounds__(kBlock) void k_rowsplit(const int* __restrict__ row
                                                       const typename S::T* __restrict__ B,
                                                       float* __restrict__ C, int64_t m, int n,
                                                       int64_t ld, int g_log2, int ts_log2) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int tl_log2 = g_log2 + ts_log2;  // lanes per team (log2), <= 6
-    const int TL = 1 << tl_log2;
-    const int team_base = lane & ~(TL - 1);
-    const int tl = lane & (TL - 1);
-    const int slot = tl >> g_log2;
-    const int g = tl & ((1 << g_log2) - 1);
-    const int col = blockIdx.y * (VEC << g_log2) + g * VEC;
-    const bool col_ok = col < n;
-    const int rpb_log2 = (6 - tl_log2) + 2;  // rows per workgroup: teams per wave * 4 waves
+    const int rpb_log2 = (6 - g_log2 - ts_log2) + 2;
     const int64_t nblk = (m + (int64_t(1) << rpb_log2) - 1) >> rpb_log2;
-
-    for (int64_t blk = xcd_remap(blockIdx.x, gridDim.x); blk < nblk; blk += gridDim.x) {
-        const int64_t row = (blk << rpb_log2) + (threadIdx.x >> tl_log2);
-        int p0 = 0, p1 = 0;
-        if (row < m) {
-            p0 = __builtin_nontemporal_load(rowptr + row);
-            p1 = __builtin_nontemporal_load(rowptr + row + 1);
-        }
-        float acc[VEC];
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
-
-        for (int base = p0; base < p1; base += TL) {
-            const int cnt = min(TL, p1 - base);
-            int my_c = 0;
-            float my_v = 0.f;
-            if (tl < cnt) {
-                my_c = __builtin_nontemporal_load(colind + base + tl);
-                my_v = load_elem(vals + base + tl, S{});
-            }
-            const int nsteps = (cnt + (1 << ts_log2) - 1) >> ts_log2;
-            for (int s = 0; s < nsteps; s += U) {
-                int c[U];
-                float v[U];
-                bool ok[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int idx = ((s + u) << ts_log2) + slot;  // entry index within the chunk
-                    ok[u] = idx < cnt;
-                    const int src = team_base + (idx & (TL - 1));
-                    c[u] = __shfl(my_c, src, kWave);
-                    const float vv = __shfl(my_v, src, kWave);
-                    v[u] = ok[u] ? vv : 0.f;
-                }
-                float b[U][VEC];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (ok[u] && col_ok) {
-                        load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v[u], b[u][e], acc[e]);
-                }
-            }
-        }
-        // Combine the team's slots (lanes G, 2G, ... apart) by a butterfly.
-        for (int off = 1 << g_log2; off < TL; off <<= 1) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[e] += __shfl_xor(acc[e], off, kWave);
-        }
-        if (slot == 0 && row < m && col_ok) store_out<VEC>(C + row * ld + col, acc);
-    }
+    for (int64_t blk = xcd_remap(blockIdx.x, gridDim.x); blk < nblk; blk += gridDim.x)
+        rowsplit_block<S, VEC, U>(rowptr, colind, vals, B, C, m, n, ld, g_log2, ts_log2, blk,
+                                  blockIdx.y);
 }
 
 template <class S, int VEC, int U>
