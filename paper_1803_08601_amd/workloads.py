@@ -322,3 +322,28 @@ def batch(seed=1005, count=512, m_lo=1_000, m_hi=200_000, n_choices=(8, 32, 128)
           values="uniform"):
     return [BatchProblem(batch_problem(seed, b, m, kind, values), n, kind)
             for b, (m, n, kind) in enumerate(batch_specs(seed, count, m_lo, m_hi, n_choices))]
+
+
+def _batch_one(args):
+    seed, b, m, kind, values = args
+    return b, batch_problem(seed, b, m, kind, values)
+
+
+def batch_parallel(seed=1005, count=512, m_lo=1_000, m_hi=200_000, n_choices=(8, 32, 128),
+                   values="uniform", workers=None):
+    """Same problems as ``batch``, generated by a process pool (each problem
+    has its own random stream, so the result does not depend on workers).
+    Workers are fresh interpreters (spawn), never forks of a process that may
+    hold a GPU context."""
+    import concurrent.futures
+    import multiprocessing
+    import os
+    specs = batch_specs(seed, count, m_lo, m_hi, n_choices)
+    workers = workers or min(16, len(os.sched_getaffinity(0)))
+    out = [None] * count
+    jobs = [(seed, b, m, kind, values) for b, (m, n, kind) in enumerate(specs)]
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        for b, A in ex.map(_batch_one, jobs, chunksize=4):
+            out[b] = BatchProblem(A, specs[b][1], specs[b][2])
+    return out

@@ -1,0 +1,168 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (plans built the same way), on sampled output rows that the
+FP64 oracle computes one by one, plus properties that hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1803_08601_amd import native as nv
+from paper_1803_08601_amd import workloads as wl
+from spmm_check import DT, TOL_F32, TOL_STORAGE_16, dev, host_bits, rel_err
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def sample_rows(A, count=1500, seed=0):
+    rng = np.random.default_rng(seed)
+    L = A.row_lengths()
+    longest = np.argsort(L)[-12:]
+    rows = np.concatenate([rng.choice(A.m, size=min(count, A.m), replace=False), longest,
+                           [0, A.m - 1]])
+    return np.unique(rows).astype(np.int64)
+
+
+def check_rows(A, vt, Bt, C, n, rows, tol=TOL_F32):
+    v, vtag = host_bits(vt)
+    b, btag = host_bits(Bt)
+    ref = oracle.spmm_rows(A.rowptr, A.colind, v, b, rows, n=n, vals_tag=vtag, b_tag=btag)
+    N = oracle.spmm_rows(A.rowptr, A.colind, v, b, rows, n=n, vals_tag=vtag, b_tag=btag, absval=True)
+    got = C[torch.from_numpy(rows).cuda()].cpu().numpy()
+    e = rel_err(got, ref, N)
+    assert e <= tol, e
+    return e
+
+
+@pytest.fixture(scope="module")
+def power_law():
+    return wl.power_law(seed=1002)
+
+
+@pytest.fixture(scope="module")
+def stencil():
+    return wl.stencil27(seed=1003)
+
+
+@pytest.mark.parametrize("n", [64, 8])
+@pytest.mark.parametrize("mode", ["autotune", "paper", "merge"])
+def test_power_law_full(power_law, n, mode):
+    A = power_law
+    B = wl.dense(1002, A.k, n)
+    rp, ci, vt, Bt = dev(A.rowptr), dev(A.colind), dev(A.vals), dev(B)
+    plan = nv.Plan(rp, ci, A.m, A.k, n, mode=mode, nnz=A.nnz)
+    C = torch.full((A.m, n), float("nan"), device="cuda")
+    plan.execute(vt, Bt, C)
+    torch.cuda.synchronize()
+    assert not torch.isnan(C).any()
+    check_rows(A, vt, Bt, C, n, sample_rows(A))
+    # any size: row sums against B = 1 (every column equals the row's value sum)
+    ones = torch.ones(A.k, n, device="cuda")
+    plan.execute(vt, ones, C)
+    torch.cuda.synchronize()
+    rs = C[:, 0].double().cpu().numpy()
+    rows = np.repeat(np.arange(A.m), A.row_lengths())
+    s = np.bincount(rows, weights=A.vals.astype(np.float64), minlength=A.m)
+    N = np.bincount(rows, weights=np.abs(A.vals.astype(np.float64)), minlength=A.m)
+    assert rel_err(rs, s, N) <= TOL_F32
+    assert torch.all(C == C[:, :1])
+
+
+@pytest.mark.parametrize("n", [16, 128])
+def test_stencil_full(stencil, n):
+    A = stencil
+    B = wl.dense(1003, A.k, n)
+    rp, ci, vt, Bt = dev(A.rowptr), dev(A.colind), dev(A.vals), dev(B)
+    for mode in ("autotune", "paper"):
+        plan = nv.Plan(rp, ci, A.m, A.k, n, mode=mode, nnz=A.nnz)
+        C = torch.full((A.m, n), float("nan"), device="cuda")
+        plan.execute(vt, Bt, C)
+        torch.cuda.synchronize()
+        check_rows(A, vt, Bt, C, n, sample_rows(A))
+        del plan
+
+
+def test_power_law_integer_exact_full(power_law):
+    """Integer values at full size: the whole output must equal the oracle
+    bit for bit, whatever the kernel and order."""
+    A = wl.CSR(power_law.rowptr, power_law.colind,
+               np.random.default_rng(1).integers(-8, 9, power_law.nnz).astype(np.float32),
+               power_law.m, power_law.k)
+    n = 8
+    B = wl.dense(3, A.k, n, kind="int")
+    rp, ci = dev(A.rowptr), dev(A.colind)
+    ref = oracle.spmm(A.rowptr, A.colind, A.vals, B)
+    for mode in ("merge", "rowsplit"):
+        plan = nv.Plan(rp, ci, A.m, A.k, n, mode=mode, nnz=A.nnz)
+        C = torch.empty(A.m, n, device="cuda")
+        plan.execute(dev(A.vals), dev(B), C)
+        torch.cuda.synchronize()
+        assert np.array_equal(C.cpu().numpy().astype(np.float64), ref)
+
+
+def test_gcn_bf16_forward_backward_full():
+    A = wl.gcn_adjacency(seed=1004)
+    n = 128
+    B = wl.dense(1004, A.k, n)
+    dC = wl.dense(1004, A.m, n, kind="normal", stream=2)
+    vt = dev(A.vals.astype(np.float32), torch.bfloat16)
+    Bt = dev(B, torch.bfloat16)
+    dCt = dev(dC)
+    rp, ci = dev(A.rowptr), dev(A.colind)
+    plan = nv.Plan(rp, ci, A.m, A.k, n, dtype=nv.SPMM_BF16, mode="autotune", nnz=A.nnz)
+    C = torch.empty(A.m, n, device="cuda")
+    plan.execute(vt, Bt, C)
+    plan.transpose_build()
+    dB = torch.empty(A.k, n, device="cuda")
+    plan.execute_t(vt, dCt, dB)
+    dv = torch.empty(A.nnz, device="cuda")
+    plan.sddmm(dCt, Bt, dv)
+    torch.cuda.synchronize()
+    rows = sample_rows(A)
+    check_rows(A, vt, Bt, C, n, rows)  # kernel error on the bf16 inputs
+    # storage error against the fp32/fp64 inputs
+    ref32 = oracle.spmm_rows(A.rowptr, A.colind, A.vals, B, rows)
+    N32 = oracle.spmm_rows(A.rowptr, A.colind, np.abs(A.vals), np.abs(B), rows)
+    assert rel_err(C[torch.from_numpy(rows).cuda()].cpu().numpy(), ref32, N32) <= TOL_STORAGE_16
+    v, vtag = host_bits(vt)
+    b, btag = host_bits(Bt)
+    ref_dv = oracle.sddmm(A.rowptr, A.colind, dC, b, b_tag=btag)
+    N_dv = oracle.sddmm(A.rowptr, A.colind, dC, b, b_tag=btag, absval=True)
+    assert rel_err(dv.cpu().numpy(), ref_dv, N_dv) <= TOL_F32
+    # symmetric A: A^T dC equals A dC, so sampled rows of dB come from the oracle product
+    ref_dB = oracle.spmm_rows(A.rowptr, A.colind, v, dC, rows, vals_tag=vtag)
+    N_dB = oracle.spmm_rows(A.rowptr, A.colind, v, dC, rows, vals_tag=vtag, absval=True)
+    assert rel_err(dB[torch.from_numpy(rows).cuda()].cpu().numpy(), ref_dB, N_dB) <= TOL_F32
+    # Euler identities of the bilinear loss
+    L = float((C.double() * dCt.double()).sum())
+    scale = float((C.abs().double() * dCt.abs().double()).sum())
+    assert abs(float((dB.double() * Bt.double()).sum()) - L) <= 1e-5 * scale
+    assert abs(float((dv.double() * vt.double()).sum()) - L) <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batched_full(dtype):
+    probs = wl.batch_parallel(seed=1005)
+    assert len(probs) == 512
+    keep, specs = [], []
+    for b, P in enumerate(probs):
+        A, n = P.A, P.n
+        B = wl.dense(1005 + b, A.k, n)
+        rp, ci = dev(A.rowptr), dev(A.colind)
+        vt, Bt = dev(A.vals, DT[dtype]), dev(B, DT[dtype])
+        C = torch.empty(A.m, n, device="cuda")
+        keep.append((A, n, vt, Bt, C, rp, ci))
+        specs.append(nv.spmm_problem(rp.data_ptr(), ci.data_ptr(), vt.data_ptr(), Bt.data_ptr(),
+                                     C.data_ptr(), A.m, A.k, A.nnz, n, n))
+    h = nv.spmm_batch_plan(specs, nv.dtype_code(DT[dtype]), nv.SPMM_MODE_AUTOTUNE)
+    try:
+        for k in keep:
+            k[4].fill_(float("nan"))
+        nv.spmm_batch_run(h)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(5)
+        for b in rng.choice(512, size=48, replace=False):
+            A, n, vt, Bt, C, _, _ = keep[b]
+            check_rows(A, vt, Bt, C, n, sample_rows(A, count=64, seed=int(b)))
+        assert not any(torch.isnan(k[4]).any().item() for k in keep)
+    finally:
+        nv.spmm_batch_destroy(h)
