@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -87,6 +89,113 @@ def make_workload(name, n):
     return A, B, desc
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def gcn_fwd_bwd(steps=20, warmup=3):
+    """Differentiable SpMM on the GCN adjacency (500k nodes, mean degree 32,
+    n = 128): one step = forward C = A B, then dB = A^T dC and dvals =
+    SDDMM(dC, B). BF16 storage of vals and B against float32 storage, both
+    with float32 accumulation; accuracy of both is checked by the test suite
+    against the FP64 oracle at full size."""
+    import torch
+    from paper_1803_08601_amd import native as nv
+    from paper_1803_08601_amd import workloads as wl
+    A = wl.gcn_adjacency(seed=1004)
+    n = 128
+    B = wl.dense(1004, A.k, n)
+    dC = torch.from_numpy(wl.dense(1004, A.m, n, kind="normal", stream=2)).cuda()
+    rp, ci = torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colind).cuda()
+    out = {"workload": "GCN normalised adjacency, 500k nodes, mean degree 32, n=128",
+           "nnz": A.nnz}
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        vals = torch.from_numpy(A.vals.astype(np.float32)).to(dt).cuda()
+        Bt = torch.from_numpy(B).to(dt).cuda()
+        plan = nv.Plan(rp, ci, A.m, A.k, n, dtype=nv.dtype_code(dt), mode="autotune", nnz=A.nnz)
+        plan.transpose_build()
+        C = torch.empty(A.m, n, device="cuda")
+        dB = torch.empty(A.k, n, device="cuda")
+        dv = torch.empty(A.nnz, device="cuda")
+        fwd = _timed(lambda: plan.execute(vals, Bt, C), steps, warmup)
+        bwd_b = _timed(lambda: plan.execute_t(vals, dC, dB), steps, warmup)
+        bwd_v = _timed(lambda: plan.sddmm(dC, Bt, dv), steps, warmup)
+
+        def step():
+            plan.execute(vals, Bt, C)
+            plan.execute_t(vals, dC, dB)
+            plan.sddmm(dC, Bt, dv)
+        total = _timed(step, steps, warmup)
+        out[name] = {"fwd_ms": round(fwd, 4), "dB_ms": round(bwd_b, 4), "dvals_ms": round(bwd_v, 4),
+                     "fwd_bwd_ms": round(total, 4),
+                     "fwd_gflops": round(2.0 * A.nnz * n / (fwd * 1e-3) / 1e9, 1),
+                     "kernel": "merge" if plan.info().config.kernel else "rowsplit"}
+        plan.close()
+    out["bf16_speedup_fwd_bwd"] = round(out["f32"]["fwd_bwd_ms"] / out["bf16"]["fwd_bwd_ms"], 3)
+    out["bf16_speedup_fwd"] = round(out["f32"]["fwd_ms"] / out["bf16"]["fwd_ms"], 3)
+    return out
+
+
+def batched(steps=10, warmup=2):
+    """512 uneven products (m = k log-uniform in [1e3, 2e5], half U{8..64}
+    rows and half Zipf-2.1 rows, n from {8, 32, 128}) in one persistent
+    launch replayed from a hipGraph, against the plain float32 kernel called
+    once per problem; float32 and BF16 storage, float32 accumulation."""
+    import torch
+    from paper_1803_08601_amd import native as nv
+    from paper_1803_08601_amd import workloads as wl
+    probs = wl.batch_parallel(seed=1005)
+    flops = sum(2.0 * p.A.nnz * p.n for p in probs)
+    out = {"workload": "512 uneven CSR products, m=k in [1e3, 2e5], n in {8, 32, 128}",
+           "problems": len(probs), "nnz": int(sum(p.A.nnz for p in probs)), "gflop": round(flops / 1e9, 2)}
+    dev = {}
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        tensors, specs = [], []
+        for b, P in enumerate(probs):
+            A, n = P.A, P.n
+            key = (b, "struct")
+            if key not in dev:
+                dev[key] = (torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colind).cuda())
+            rp, ci = dev[key]
+            vt = torch.from_numpy(A.vals).to(dt).cuda()
+            Bt = torch.from_numpy(wl.dense(1005 + b, A.k, n)).to(dt).cuda()
+            C = torch.empty(A.m, n, device="cuda")
+            tensors.append((vt, Bt, C))
+            specs.append(nv.spmm_problem(rp.data_ptr(), ci.data_ptr(), vt.data_ptr(), Bt.data_ptr(),
+                                         C.data_ptr(), A.m, A.k, A.nnz, n, n))
+        t0 = time.perf_counter()
+        h = nv.spmm_batch_plan(specs, nv.dtype_code(dt), nv.SPMM_MODE_AUTOTUNE)
+        plan_s = time.perf_counter() - t0
+        ms = _timed(lambda: nv.spmm_batch_run(h), steps, warmup)
+        kinds = [nv.spmm_batch_problem_config(h, b).kernel for b in range(len(probs))]
+        nv.spmm_batch_destroy(h)
+        rec = {"graph_ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+               "plan_s": round(plan_s, 2), "merge_problems": int(sum(kinds))}
+        if name == "f32":
+            plans = [nv.Plan(dev[(b, "struct")][0], dev[(b, "struct")][1], P.A.m, P.A.k, P.n,
+                             mode="paper", nnz=P.A.nnz) for b, P in enumerate(probs)]
+
+            def per_problem():
+                for pl, (vt, Bt, C) in zip(plans, tensors):
+                    pl.execute(vt, Bt, C)
+            rec["plain_per_problem_ms"] = round(_timed(per_problem, max(2, steps // 2), 1), 4)
+            for pl in plans:
+                pl.close()
+        out[name] = rec
+        del tensors, specs
+    out["batched_speedup_vs_plain_f32"] = round(out["f32"]["plain_per_problem_ms"] / out["f32"]["graph_ms"], 3)
+    out["bf16_batched_speedup_vs_plain_f32"] = round(out["f32"]["plain_per_problem_ms"] / out["bf16"]["graph_ms"], 3)
+    return out
+
+
 def cpu_baseline(A, B, n, budget_s=10.0, max_reps=8):
     import numpy as np
     import oracle
@@ -114,6 +223,8 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--mode", default="autotune", choices=["autotune", "paper", "rowsplit", "merge"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the headline product (skip the GCN fwd+bwd and batched extras)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -211,6 +322,11 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, n)
+    if not args.quick:
+        del C, Bt, vals
+        plan.close()
+        torch.cuda.empty_cache()
+        out["extra"] = {"gcn_fwd_bwd": gcn_fwd_bwd(), "batched": batched()}
     print(json.dumps(out), flush=True)
 
 
