@@ -209,10 +209,13 @@ static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_
     slot_geometry(p.n, vec, &g_log2, &tiles);
     std::vector<int> unrolls = {2, 4, 8};
     if (fixed_unroll) unrolls = {fixed_unroll};
-    for (int lpr = 1 << g_log2; lpr <= spmmk::kWaveSize; lpr *= 2)
-        for (int u : unrolls) out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024});
-    for (int W : {512, 1024, 2048, 4096})
+    // Merge-based first: its time does not depend on row lengths, so it sets
+    // a bar that lets hopeless row-split shapes stop after one run. Row split
+    // goes from whole-wavefront teams (best for long rows) down.
+    for (int W : {2048, 1024, 4096, 512})
         for (int u : unrolls) out.push_back({SPMM_KERNEL_MERGE, vec, 1 << g_log2, u, W});
+    for (int lpr = spmmk::kWaveSize; lpr >= (1 << g_log2); lpr /= 2)
+        for (int u : unrolls) out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024});
     return out;
 }
 
@@ -273,9 +276,14 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     TUNE_HIP(hipEventCreate(&e0));
     TUNE_HIP(hipEventCreate(&e1));
 
+    // Candidates within kTie of the fastest count as equal; the earliest in
+    // candidate order wins, so repeated tuning of one matrix picks one shape.
+    constexpr double kTie = 1.03;
     double best = 1e30;
-    spmm_config best_cfg{};
+    std::vector<std::pair<spmm_config, double>> timed;
+    int slow_rowsplit = 0;
     for (spmm_config c : tune_candidates(p, fixed_unroll)) {
+        if (c.kernel == SPMM_KERNEL_ROWSPLIT && slow_rowsplit >= 3) break;
         spmm_plan_s q = p;  // shallow copy: never destroyed
         q.ws = MergeWs{};
         if (check_config(q, c) != SPMM_OK) continue;
@@ -295,23 +303,34 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
             float ms = 0.f;
             TUNE_HIP(hipEventElapsedTime(&ms, e0, e1));
             if (rep > 0) times.push_back(ms);
-            if (rep == 0 && ms > 4.0 * best) break;  // clearly slower: skip the timed reps
+            if (rep == 0 && ms > 2.0 * best) break;  // clearly slower: skip the timed reps
         }
-        if (times.empty()) continue;
+        if (times.empty()) {
+            if (c.kernel == SPMM_KERNEL_ROWSPLIT) ++slow_rowsplit;
+            continue;
+        }
         std::sort(times.begin(), times.end());
         const double med = times[times.size() / 2];
-        if (med < best) {
-            best = med;
-            best_cfg = c;
+        if (c.kernel == SPMM_KERNEL_ROWSPLIT) slow_rowsplit = med > 3.0 * best ? slow_rowsplit + 1 : 0;
+        best = std::min(best, med);
+        timed.push_back({c, med});
+    }
+    spmm_config best_cfg{};
+    double best_ms = 1e30;
+    for (const auto& t : timed) {
+        if (t.second <= best * kTie) {
+            best_cfg = t.first;
+            best_ms = t.second;
+            break;
         }
     }
     cleanup();
 #undef TUNE_HIP
-    if (best >= 1e30) return fail(SPMM_ERR_UNSUPPORTED, "autotune: no candidate ran");
+    if (best_ms >= 1e30) return fail(SPMM_ERR_UNSUPPORTED, "autotune: no candidate ran");
     p.cfg = best_cfg;
-    p.tuned_ms = best;
+    p.tuned_ms = best_ms;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tuned[key] = {best_cfg, best};
+    g_tuned[key] = {best_cfg, best_ms};
     return SPMM_OK;
 }
 

@@ -23,6 +23,7 @@ struct spmm_batch_s {
     int64_t* d_item_off = nullptr;
     int* d_merge_ids = nullptr;
     int64_t* d_piece_off = nullptr;
+    int64_t* d_queues = nullptr;
     unsigned long long* d_counter = nullptr;
     int nprob = 0, nmerge = 0, grid = 1;
     int64_t total_items = 0, total_pieces = 0;
@@ -49,7 +50,7 @@ void free_batch(spmm_batch_s* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     for (void* p : {(void*)b->d_probs, (void*)b->d_item_off, (void*)b->d_merge_ids,
-                    (void*)b->d_piece_off, (void*)b->d_counter})
+                    (void*)b->d_piece_off, (void*)b->d_queues, (void*)b->d_counter})
         if (p) (void)hipFree(p);
     for (auto* p : b->plans) destroy_plan(p);
     delete b;
@@ -57,8 +58,8 @@ void free_batch(spmm_batch_s* b) {
 
 int launch(const spmm_batch_s& b, hipStream_t st) {
     hipError_t e = spmmk::launch_batch(b.dtype, b.grid, b.lds, b.d_probs, b.d_item_off, b.nprob,
-                                       b.total_items, b.d_counter, b.d_merge_ids, b.d_piece_off,
-                                       b.nmerge, b.total_pieces, st);
+                                       b.total_items, b.d_queues, b.d_counter, b.d_merge_ids,
+                                       b.d_piece_off, b.nmerge, b.total_pieces, st);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
     return SPMM_OK;
 }
@@ -152,21 +153,41 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
         }
         work.push_back({i, tile_cost, bp});
     }
-    std::stable_sort(work.begin(), work.end(),
-                     [](const Entry& a, const Entry& c) { return a.cost > c.cost; });
+    // Bin-pack problems into one queue per XCD: longest total first onto the
+    // lightest queue; inside a queue, costliest tiles first.
+    constexpr int NQ = spmmk::kBatchQueues;
+    std::vector<int> order(work.size());
+    std::iota(order.begin(), order.end(), 0);
+    auto total_cost = [&](int i) { return work[i].cost * double(work[i].bp.items); };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return total_cost(a) > total_cost(c); });
+    std::vector<std::vector<int>> bins(NQ);
+    std::vector<double> load(NQ, 0.0);
+    for (int i : order) {
+        const int q = int(std::min_element(load.begin(), load.end()) - load.begin());
+        bins[q].push_back(i);
+        load[q] += total_cost(i);
+    }
     std::vector<spmmk::BatchProb> probs;
-    std::vector<int64_t> item_off, piece_off;
+    std::vector<int64_t> item_off, piece_off, queues(2 * NQ, 0);
     std::vector<int> merge_ids;
     int64_t items = 0, pieces = 0;
-    for (const Entry& w : work) {
-        if (w.bp.kernel == SPMM_KERNEL_MERGE && w.bp.P > 0) {
-            merge_ids.push_back((int)probs.size());
-            piece_off.push_back(pieces);
-            pieces += w.bp.P;
+    for (int q = 0; q < NQ; ++q) {
+        std::stable_sort(bins[q].begin(), bins[q].end(),
+                         [&](int a, int c) { return work[a].cost > work[c].cost; });
+        queues[q] = items;
+        for (int i : bins[q]) {
+            const Entry& w = work[i];
+            if (w.bp.kernel == SPMM_KERNEL_MERGE && w.bp.P > 0) {
+                merge_ids.push_back((int)probs.size());
+                piece_off.push_back(pieces);
+                pieces += w.bp.P;
+            }
+            item_off.push_back(items);
+            items += w.bp.items;
+            probs.push_back(w.bp);
         }
-        item_off.push_back(items);
-        items += w.bp.items;
-        probs.push_back(w.bp);
+        queues[NQ + q] = items - queues[q];
     }
     b->nprob = (int)probs.size();
     b->nmerge = (int)merge_ids.size();
@@ -176,8 +197,9 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
     if (rc == SPMM_OK) rc = upload(&b->d_item_off, item_off, st);
     if (rc == SPMM_OK) rc = upload(&b->d_merge_ids, merge_ids, st);
     if (rc == SPMM_OK) rc = upload(&b->d_piece_off, piece_off, st);
+    if (rc == SPMM_OK) rc = upload(&b->d_queues, queues, st);
     if (rc == SPMM_OK) {
-        e = hipMalloc(&b->d_counter, sizeof(unsigned long long));
+        e = hipMalloc(&b->d_counter, sizeof(unsigned long long) * NQ);
         if (e != hipSuccess) rc = hip_fail(e, "hipMalloc counter");
     }
     if (rc == SPMM_OK) {

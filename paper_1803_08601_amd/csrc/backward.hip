@@ -216,7 +216,7 @@ hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int
 // by binary search, and walks them in order, reloading its dC row chunk only
 // when the row changes. Per entry it gathers the B row chunk, forms VEC
 // partial products, loops over the column tiles, and reduces the slot's
-// lanes with a butterfly; lane 0 of the slot writes dvals[p]. The split is
+// lanes with DPP row exchanges; lane 0 of the slot writes dvals[p]. The split is
 // independent of row lengths, so long rows cost no more than short ones.
 template <class S, int VEC, int U>
 __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr,
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            for (int off = 1; off < G; off <<= 1) part[u] += __shfl_xor(part[u], off, kWave);
+            part[u] = group_sum(part[u], g_log2);
             if (g == 0 && pb + u < p1) __builtin_nontemporal_store(part[u], dvals + pb + u);
         }
     }

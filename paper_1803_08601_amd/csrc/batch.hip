@@ -3,34 +3,55 @@
 //
 // The host lays out a work list: every problem contributes its tiles - a
 // workgroup's rows for row-split problems, a merge piece for merge-based
-// problems - times its column tiles, problems with the costliest tiles first.
-// A grid of exactly as many workgroups as fit on the GPU at once takes tiles
-// from one atomic counter until the list is exhausted; each tile runs the same
-// device function as the single-product kernels, with that problem's shape.
-// The counter only grows, so every workgroup reaches the end of the list and
-// exits. A second launch adds the carry-outs of all merge-based problems
-// (Phase 3), and a one-thread kernel re-arms the counter for the next run.
+// problems - times its column tiles. Problems are bin-packed by cost into one
+// queue per XCD (longest first onto the lightest queue), so that a problem's
+// B rows are pulled into one XCD's L2 rather than all eight. A grid of exactly
+// as many workgroups as fit on the GPU at once starts on the queue of its
+// XCD (workgroup b runs on XCD b mod 8) and takes tiles from that queue's
+// atomic counter; when the queue is exhausted it moves on to the next queue,
+// so the tails of the queues are shared. Counters only grow, so every
+// workgroup finds every queue exhausted after finitely many attempts and
+// exits. Each tile runs the same device function as the single-product
+// kernels, with that problem's shape. A second launch adds the carry-outs of
+// all merge-based problems (Phase 3), and a small kernel re-arms the counters
+// for the next run.
 
 #include "batch.hpp"
 #include "tiles.hpp"
 
 namespace spmmk {
 
-__global__ void k_batch_reset(unsigned long long* counter) { *counter = 0ull; }
+__global__ void k_batch_reset(unsigned long long* counters) {
+    if (threadIdx.x < kBatchQueues) counters[threadIdx.x] = 0ull;
+}
 
 template <class S, int U>
 __global__ __launch_bounds__(kBlock) void k_batch(const BatchProb* __restrict__ probs,
                                                    const int64_t* __restrict__ item_off,
-                                                   int nprob, int64_t total,
-                                                   unsigned long long* __restrict__ counter) {
+                                                   int nprob, const int64_t* __restrict__ queues,
+                                                   unsigned long long* __restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t s_item;
+    int q = blockIdx.x % kBatchQueues;  // queue of this workgroup's XCD
+    int exhausted = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(counter, 1ull);
+        if (threadIdx.x == 0) {
+            int64_t it = -1;
+            while (exhausted < kBatchQueues) {
+                const int64_t i = (int64_t)atomicAdd(&counters[q], 1ull);
+                if (i < queues[kBatchQueues + q]) {
+                    it = queues[q] + i;
+                    break;
+                }
+                q = (q + 1) % kBatchQueues;
+                ++exhausted;
+            }
+            s_item = it;
+        }
         __syncthreads();
         const int64_t it = s_item;
         __syncthreads();  // everyone has read s_item before it is overwritten
-        if (it >= total) break;
+        if (it < 0) break;
         int lo = 0, hi = nprob - 1;  // last problem whose first item is <= it
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -108,18 +129,18 @@ hipError_t batch_grid(int dtype, size_t lds, int* grid) {
 
 hipError_t launch_batch(int dtype, int grid, size_t lds, const BatchProb* probs,
                         const int64_t* item_off, int nprob, int64_t total,
-                        unsigned long long* counter, const int* merge_ids,
-                        const int64_t* piece_off, int nmerge, int64_t total_pieces,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, counter);
+                        const int64_t* queues, unsigned long long* counters,
+                        const int* merge_ids, const int64_t* piece_off, int nmerge,
+                        int64_t total_pieces, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kWave), 0, st, counters);
     if (total > 0) {
         switch (dtype) {
         case 0: hipLaunchKernelGGL((k_batch<F32, kBatchUnroll>), dim3(grid), dim3(kBlock), lds, st,
-                                   probs, item_off, nprob, total, counter); break;
+                                   probs, item_off, nprob, queues, counters); break;
         case 1: hipLaunchKernelGGL((k_batch<BF16, kBatchUnroll>), dim3(grid), dim3(kBlock), lds, st,
-                                   probs, item_off, nprob, total, counter); break;
+                                   probs, item_off, nprob, queues, counters); break;
         case 2: hipLaunchKernelGGL((k_batch<F16, kBatchUnroll>), dim3(grid), dim3(kBlock), lds, st,
-                                   probs, item_off, nprob, total, counter); break;
+                                   probs, item_off, nprob, queues, counters); break;
         default: return hipErrorInvalidValue;
         }
     }

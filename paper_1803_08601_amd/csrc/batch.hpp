@@ -9,6 +9,8 @@ namespace spmmk {
 // Unroll of the batched kernel: one instantiation keeps its register use
 // (and so its occupancy) independent of the mix of problems.
 constexpr int kBatchUnroll = 4;
+// One work queue per XCD.
+constexpr int kBatchQueues = 8;
 
 struct BatchProb {
     const int* rowptr;
@@ -36,10 +38,12 @@ struct BatchProb {
 // Workgroups of the persistent kernel that fit on the device at once.
 hipError_t batch_grid(int dtype, size_t lds, int* grid);
 
+// queues: kBatchQueues first-item offsets followed by kBatchQueues lengths;
+// counters: kBatchQueues counters (re-armed by the launch).
 hipError_t launch_batch(int dtype, int grid, size_t lds, const BatchProb* probs,
                         const int64_t* item_off, int nprob, int64_t total,
-                        unsigned long long* counter, const int* merge_ids,
-                        const int64_t* piece_off, int nmerge, int64_t total_pieces,
-                        hipStream_t st);
+                        const int64_t* queues, unsigned long long* counters,
+                        const int* merge_ids, const int64_t* piece_off, int nmerge,
+                        int64_t total_pieces, hipStream_t st);
 
 }  // namespace spmmk

@@ -132,6 +132,29 @@ __device__ __forceinline__ void store_f32(float* p, const float (&a)[VEC]) {
     }
 }
 
+// Sum over aligned groups of 2^glog2 lanes (glog2 <= 6); every lane of a
+// group receives its group's sum. Within 16-lane rows the exchanges are DPP
+// moves (quad permutations, then the half-row and row mirrors), which stay
+// inside the group at every step; wider groups exchange across rows with
+// ds_bpermute. All lanes of a group must be active.
+__device__ __forceinline__ float dpp_add(float v, int step) {
+    int x = __float_as_int(v);
+    switch (step) {
+    case 0: x = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); break;   // quad_perm [1,0,3,2]
+    case 1: x = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false); break;   // quad_perm [2,3,0,1]
+    case 2: x = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false); break;  // row_half_mirror
+    default: x = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false); break; // row_mirror
+    }
+    return v + __int_as_float(x);
+}
+
+__device__ __forceinline__ float group_sum(float v, int glog2) {
+    const int in_row = glog2 < 4 ? glog2 : 4;
+    for (int s = 0; s < in_row; ++s) v = dpp_add(v, s);
+    for (int off = 16; off < (1 << glog2); off <<= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
 // Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD
 // b mod 8). Renumber them so that each XCD works on one contiguous range of
 // logical tiles: neighbouring rows then share that XCD's L2. A bijection on

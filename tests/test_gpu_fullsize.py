@@ -166,3 +166,36 @@ def test_batched_full(dtype):
         assert not any(torch.isnan(k[4]).any().item() for k in keep)
     finally:
         nv.spmm_batch_destroy(h)
+
+
+@pytest.mark.parametrize("kernel", ["rowsplit", "merge"])
+def test_large_indices(kernel):
+    """Row offsets near 2^31 and row * ld beyond 2^31 elements: 64-bit
+    address arithmetic in every kernel (and the row-split grid-stride loop).
+    Structure and integer values are drawn on the device (seeded); the rows
+    sampled for the oracle are copied out with their entries, and integer
+    values make the comparison exact."""
+    m, k, n = 40_000_000, 5_000_000, 64          # C has 2.56e9 elements
+    per = 50                                      # nnz = 2.0e9 < 2^31
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2024)
+    rp = torch.arange(0, (m + 1) * per, per, dtype=torch.int64, device="cuda").to(torch.int32)
+    ci = torch.randint(0, k, (m * per,), generator=g, device="cuda", dtype=torch.int32)
+    vt = torch.randint(-8, 9, (m * per,), generator=g, device="cuda", dtype=torch.int32).to(torch.bfloat16)
+    Bt = torch.randint(-8, 9, (k, n), generator=g, device="cuda", dtype=torch.int32).to(torch.bfloat16)
+    C = torch.empty(m, n, device="cuda")
+    plan = nv.Plan(rp, ci, m, k, n, dtype=nv.SPMM_BF16, mode=kernel, nnz=m * per)
+    plan.execute(vt, Bt, C)
+    torch.cuda.synchronize()
+    rows = np.array([0, 1, 12345, m // 2, 38_654_703, m - 2, m - 1], dtype=np.int64)
+    idx = torch.from_numpy((rows[:, None] * per + np.arange(per)[None, :]).reshape(-1)).cuda()
+    sub_ci = ci[idx].cpu().numpy()
+    sub_v, vtag = host_bits(vt[idx])
+    b_bits, btag = host_bits(Bt)
+    sub_rp = np.arange(0, (len(rows) + 1) * per, per, dtype=np.int32)
+    ref = oracle.spmm(sub_rp, sub_ci, sub_v, b_bits, vals_tag=vtag, b_tag=btag)
+    got = C[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, ref)
+    plan.close()
+    del C, ci, vt, Bt, rp
+    torch.cuda.empty_cache()
