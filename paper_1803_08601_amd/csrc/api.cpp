@@ -201,7 +201,8 @@ struct TuneKey {
 };
 static std::map<TuneKey, std::pair<spmm_config, double>> g_tuned;
 
-static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_unroll) {
+static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_unroll,
+                                                int max_W) {
     std::vector<spmm_config> out;
     const int v16 = vec16(p.dtype);
     const int vec = (p.n % v16 == 0 && p.ld % v16 == 0) ? v16 : 1;
@@ -213,7 +214,8 @@ static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_
     // a bar that lets hopeless row-split shapes stop after one run. Row split
     // goes from whole-wavefront teams (best for long rows) down.
     for (int W : {2048, 1024, 4096, 512})
-        for (int u : unrolls) out.push_back({SPMM_KERNEL_MERGE, vec, 1 << g_log2, u, W});
+        if (!max_W || W <= max_W)
+            for (int u : unrolls) out.push_back({SPMM_KERNEL_MERGE, vec, 1 << g_log2, u, W});
     for (int lpr = spmmk::kWaveSize; lpr >= (1 << g_log2); lpr /= 2)
         for (int u : unrolls) out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024});
     return out;
@@ -221,9 +223,10 @@ static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_
 
 static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     const int fixed_unroll = opts ? opts->fixed_unroll : 0;
+    const int max_W = opts ? opts->max_W : 0;
     const bool own = opts && opts->C && (p.nnz == 0 || (opts->vals && opts->B));
     const TuneKey key{p.device, p.m, p.k, p.nnz, p.n, p.ld, p.max_row_len, p.long_rows, p.dtype,
-                      fixed_unroll};
+                      fixed_unroll * 65536 + max_W};
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tuned.find(key);
@@ -282,7 +285,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     double best = 1e30;
     std::vector<std::pair<spmm_config, double>> timed;
     int slow_rowsplit = 0;
-    for (spmm_config c : tune_candidates(p, fixed_unroll)) {
+    for (spmm_config c : tune_candidates(p, fixed_unroll, max_W)) {
         if (c.kernel == SPMM_KERNEL_ROWSPLIT && slow_rowsplit >= 3) break;
         spmm_plan_s q = p;  // shallow copy: never destroyed
         q.ws = MergeWs{};
@@ -420,6 +423,8 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
             rc = check_config(*p, p->cfg);
         }
     }
+    if (rc == SPMM_OK && opts && opts->max_W && p->cfg.items_per_wg > opts->max_W)
+        p->cfg.items_per_wg = opts->max_W;
     if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_MERGE)
         rc = prepare_merge(*p, p->ws, p->cfg.items_per_wg, st);
     if (rc == SPMM_OK) {

@@ -19,8 +19,8 @@ struct spmm_batch_s {
     int32_t dtype = 0;
     std::vector<spmm_plan_s*> plans;     // one per problem, in the caller's order
     std::vector<spmm_problem> problems;
-    spmmk::BatchProb* d_probs = nullptr;  // problems with work, in work-list order
-    int64_t* d_item_off = nullptr;
+    spmmk::BatchProb* d_probs = nullptr;  // problems with work
+    spmmk::WorkItem* d_items = nullptr;
     int* d_merge_ids = nullptr;
     int64_t* d_piece_off = nullptr;
     int64_t* d_queues = nullptr;
@@ -49,7 +49,7 @@ void free_batch(spmm_batch_s* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    for (void* p : {(void*)b->d_probs, (void*)b->d_item_off, (void*)b->d_merge_ids,
+    for (void* p : {(void*)b->d_probs, (void*)b->d_items, (void*)b->d_merge_ids,
                     (void*)b->d_piece_off, (void*)b->d_queues, (void*)b->d_counter})
         if (p) (void)hipFree(p);
     for (auto* p : b->plans) destroy_plan(p);
@@ -57,7 +57,7 @@ void free_batch(spmm_batch_s* b) {
 }
 
 int launch(const spmm_batch_s& b, hipStream_t st) {
-    hipError_t e = spmmk::launch_batch(b.dtype, b.grid, b.lds, b.d_probs, b.d_item_off, b.nprob,
+    hipError_t e = spmmk::launch_batch(b.dtype, b.grid, b.lds, b.d_probs, b.d_items,
                                        b.total_items, b.d_queues, b.d_counter, b.d_merge_ids,
                                        b.d_piece_off, b.nmerge, b.total_pieces, st);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
@@ -105,6 +105,7 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
         if (rc != SPMM_OK) break;
         TuneOpts opts;
         opts.fixed_unroll = spmmk::kBatchUnroll;
+        opts.max_W = spmmk::kBatchMaxW;
         opts.vals = q.A_vals;
         opts.B = q.B;
         opts.C = q.C;
@@ -120,8 +121,8 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
     }
     if (rc != SPMM_OK) { free_batch(b); return rc; }
 
-    // Work list: problems with work, costliest tiles first.
-    struct Entry { int64_t idx; double cost; spmmk::BatchProb bp; };
+    // Problems with work, their tile size and cost.
+    struct Entry { double tile_cost; int64_t tiles; int per_item; spmmk::BatchProb bp; };
     std::vector<Entry> work;
     for (int64_t i = 0; i < count; ++i) {
         const spmm_plan_s& p = *b->plans[i];
@@ -135,30 +136,35 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
         bp.m = p.m; bp.ld = p.ld; bp.n = (int)p.n;
         bp.kernel = p.cfg.kernel; bp.vec = vec; bp.g_log2 = s.g_log2; bp.ts_log2 = s.ts_log2;
         bp.W = s.W; bp.col_tiles = s.col_tiles;
-        double tile_cost;
         const double mean = double(p.nnz) / double(p.m);
         const double tile_cols = std::min<double>(double(p.n), double(vec << s.g_log2));
+        Entry en{};
+        double entries_per_tile;
         if (p.cfg.kernel == SPMM_KERNEL_ROWSPLIT) {
             const int64_t rows_per_block = int64_t(spmmk::kWaveSize >> (s.g_log2 + s.ts_log2)) *
                                            (spmmk::kBlock / spmmk::kWaveSize);
-            bp.items = ((p.m + rows_per_block - 1) / rows_per_block) * s.col_tiles;
-            tile_cost = rows_per_block * (1.0 + mean) * tile_cols;
+            en.tiles = (p.m + rows_per_block - 1) / rows_per_block;
+            entries_per_tile = double(rows_per_block) * (1.0 + mean);
         } else {
             bp.coords = p.ws.coords; bp.carry_vals = p.ws.carry_vals; bp.carry_rows = p.ws.carry_rows;
             bp.P = p.ws.P;
-            bp.items = p.ws.P * s.col_tiles;
-            tile_cost = double(s.W) * tile_cols;
-            spmmk::Shape ls = s;
-            b->lds = std::max(b->lds, spmmk::merge_lds_bytes(dtype, ls));
+            en.tiles = p.ws.P;
+            entries_per_tile = double(s.W);
+            b->lds = std::max(b->lds, spmmk::merge_lds_bytes(dtype, s));
         }
-        work.push_back({i, tile_cost, bp});
+        en.tile_cost = entries_per_tile * tile_cols;
+        en.per_item = (int)std::max(1.0, std::round(spmmk::kBatchItemEntries / entries_per_tile));
+        en.bp = bp;
+        work.push_back(en);
     }
-    // Bin-pack problems into one queue per XCD: longest total first onto the
+    // Bin-pack problems into one queue per XCD: largest total first onto the
     // lightest queue; inside a queue, costliest tiles first.
     constexpr int NQ = spmmk::kBatchQueues;
     std::vector<int> order(work.size());
     std::iota(order.begin(), order.end(), 0);
-    auto total_cost = [&](int i) { return work[i].cost * double(work[i].bp.items); };
+    auto total_cost = [&](int i) {
+        return work[i].tile_cost * double(work[i].tiles) * work[i].bp.col_tiles;
+    };
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return total_cost(a) > total_cost(c); });
     std::vector<std::vector<int>> bins(NQ);
@@ -169,32 +175,36 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
         load[q] += total_cost(i);
     }
     std::vector<spmmk::BatchProb> probs;
-    std::vector<int64_t> item_off, piece_off, queues(2 * NQ, 0);
+    std::vector<spmmk::WorkItem> witems;
+    std::vector<int64_t> piece_off, queues(2 * NQ, 0);
     std::vector<int> merge_ids;
-    int64_t items = 0, pieces = 0;
+    int64_t pieces = 0;
     for (int q = 0; q < NQ; ++q) {
         std::stable_sort(bins[q].begin(), bins[q].end(),
-                         [&](int a, int c) { return work[a].cost > work[c].cost; });
-        queues[q] = items;
+                         [&](int a, int c) { return work[a].tile_cost > work[c].tile_cost; });
+        queues[q] = (int64_t)witems.size();
         for (int i : bins[q]) {
             const Entry& w = work[i];
+            const int pid = (int)probs.size();
             if (w.bp.kernel == SPMM_KERNEL_MERGE && w.bp.P > 0) {
-                merge_ids.push_back((int)probs.size());
+                merge_ids.push_back(pid);
                 piece_off.push_back(pieces);
                 pieces += w.bp.P;
             }
-            item_off.push_back(items);
-            items += w.bp.items;
+            for (int ct = 0; ct < w.bp.col_tiles; ++ct)
+                for (int64_t t = 0; t < w.tiles; t += w.per_item)
+                    witems.push_back({pid, ct, (int)t, (int)std::min<int64_t>(w.per_item, w.tiles - t)});
             probs.push_back(w.bp);
         }
-        queues[NQ + q] = items - queues[q];
+        queues[NQ + q] = (int64_t)witems.size() - queues[q];
     }
+    const int64_t items = (int64_t)witems.size();
     b->nprob = (int)probs.size();
     b->nmerge = (int)merge_ids.size();
     b->total_items = items;
     b->total_pieces = pieces;
     if (rc == SPMM_OK) rc = upload(&b->d_probs, probs, st);
-    if (rc == SPMM_OK) rc = upload(&b->d_item_off, item_off, st);
+    if (rc == SPMM_OK) rc = upload(&b->d_items, witems, st);
     if (rc == SPMM_OK) rc = upload(&b->d_merge_ids, merge_ids, st);
     if (rc == SPMM_OK) rc = upload(&b->d_piece_off, piece_off, st);
     if (rc == SPMM_OK) rc = upload(&b->d_queues, queues, st);

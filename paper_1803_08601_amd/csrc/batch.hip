@@ -1,9 +1,10 @@
 // Batched SpMM: many independent products C_b = A_b B_b in one persistent
 // kernel (not in the paper; it applies the paper's two kernels per problem).
 //
-// The host lays out a work list: every problem contributes its tiles - a
-// workgroup's rows for row-split problems, a merge piece for merge-based
-// problems - times its column tiles. Problems are bin-packed by cost into one
+// The host lays out a work list: every problem contributes work items - runs
+// of row blocks (a workgroup's rows each) for row-split problems, runs of
+// merge pieces for merge-based problems, about kBatchItemEntries entries per
+// item - per column tile. Problems are bin-packed by cost into one
 // queue per XCD (longest first onto the lightest queue), so that a problem's
 // B rows are pulled into one XCD's L2 rather than all eight. A grid of exactly
 // as many workgroups as fit on the GPU at once starts on the queue of its
@@ -25,62 +26,77 @@ __global__ void k_batch_reset(unsigned long long* counters) {
     if (threadIdx.x < kBatchQueues) counters[threadIdx.x] = 0ull;
 }
 
+// Next work item for this workgroup (thread 0 only): from its current queue,
+// moving on through the other queues as they run dry; -1 when all are.
+__device__ __forceinline__ int64_t take_item(const int64_t* __restrict__ queues,
+                                             unsigned long long* __restrict__ counters, int& q,
+                                             int& exhausted) {
+    while (exhausted < kBatchQueues) {
+        const int64_t i = (int64_t)atomicAdd(&counters[q], 1ull);
+        if (i < queues[kBatchQueues + q]) return queues[q] + i;
+        q = (q + 1) % kBatchQueues;
+        ++exhausted;
+    }
+    return -1;
+}
+
 template <class S, int U>
 __global__ __launch_bounds__(kBlock) void k_batch(const BatchProb* __restrict__ probs,
-                                                   const int64_t* __restrict__ item_off,
-                                                   int nprob, const int64_t* __restrict__ queues,
+                                                   const WorkItem* __restrict__ items,
+                                                   const int64_t* __restrict__ queues,
                                                    unsigned long long* __restrict__ counters) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t s_item;
     int q = blockIdx.x % kBatchQueues;  // queue of this workgroup's XCD
     int exhausted = 0;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            int64_t it = -1;
-            while (exhausted < kBatchQueues) {
-                const int64_t i = (int64_t)atomicAdd(&counters[q], 1ull);
-                if (i < queues[kBatchQueues + q]) {
-                    it = queues[q] + i;
-                    break;
-                }
-                q = (q + 1) % kBatchQueues;
-                ++exhausted;
-            }
-            s_item = it;
-        }
-        __syncthreads();
-        const int64_t it = s_item;
-        __syncthreads();  // everyone has read s_item before it is overwritten
-        if (it < 0) break;
-        int lo = 0, hi = nprob - 1;  // last problem whose first item is <= it
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (item_off[mid] <= it) lo = mid; else hi = mid - 1;
-        }
-        const BatchProb& p = probs[lo];
-        const int64_t local = it - item_off[lo];
-        const int coltile = (int)(local % p.col_tiles);
-        const int64_t idx = local / p.col_tiles;
+    if (threadIdx.x == 0) s_item = take_item(queues, counters, q, exhausted);
+    __syncthreads();
+    int64_t it = s_item;
+    while (it >= 0) {
+        // Claim a slot of the current queue now and look at it only after
+        // this item's work, so the atomic's latency overlaps that work.
+        unsigned long long claim = 0;
+        if (threadIdx.x == 0 && exhausted < kBatchQueues) claim = atomicAdd(&counters[q], 1ull);
+        const WorkItem w = items[it];
+        const BatchProb& p = probs[w.prob];
         const typename S::T* vals = static_cast<const typename S::T*>(p.vals);
         const typename S::T* B = static_cast<const typename S::T*>(p.B);
-        if (p.kernel == 0) {
-            if (p.vec == 1)
-                rowsplit_block<S, 1, U>(p.rowptr, p.colind, vals, B, p.C, p.m, p.n, p.ld,
-                                        p.g_log2, p.ts_log2, idx, coltile);
-            else
-                rowsplit_block<S, S::kVec16, U>(p.rowptr, p.colind, vals, B, p.C, p.m, p.n, p.ld,
-                                                p.g_log2, p.ts_log2, idx, coltile);
-        } else {
-            if (p.vec == 1)
-                merge_tile<S, 1, U>(p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n, p.ld,
-                                    p.g_log2, p.coords, p.W, p.carry_vals, p.carry_rows,
-                                    (int)idx, coltile, smem);
-            else
-                merge_tile<S, S::kVec16, U>(p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n,
-                                            p.ld, p.g_log2, p.coords, p.W, p.carry_vals,
-                                            p.carry_rows, (int)idx, coltile, smem);
+        for (int t = w.first; t < w.first + w.count; ++t) {
+            if (p.kernel == 0) {
+                if (p.vec == 1)
+                    rowsplit_block<S, 1, U>(p.rowptr, p.colind, vals, B, p.C, p.m, p.n, p.ld,
+                                            p.g_log2, p.ts_log2, t, w.coltile);
+                else
+                    rowsplit_block<S, S::kVec16, U>(p.rowptr, p.colind, vals, B, p.C, p.m, p.n,
+                                                    p.ld, p.g_log2, p.ts_log2, t, w.coltile);
+            } else {
+                if (p.vec == 1)
+                    merge_tile<S, 1, U>(p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n, p.ld,
+                                        p.g_log2, p.coords, p.W, p.carry_vals, p.carry_rows, t,
+                                        w.coltile, smem);
+                else
+                    merge_tile<S, S::kVec16, U>(p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n,
+                                                p.ld, p.g_log2, p.coords, p.W, p.carry_vals,
+                                                p.carry_rows, t, w.coltile, smem);
+                __syncthreads();  // LDS is reused by the next piece
+            }
         }
-        __syncthreads();  // LDS is reused by the next tile
+        __syncthreads();  // every thread has read s_item for this item
+        if (threadIdx.x == 0) {
+            int64_t next = -1;
+            if (exhausted < kBatchQueues) {
+                if ((int64_t)claim < queues[kBatchQueues + q]) {
+                    next = queues[q] + (int64_t)claim;
+                } else {
+                    q = (q + 1) % kBatchQueues;
+                    ++exhausted;
+                    next = take_item(queues, counters, q, exhausted);
+                }
+            }
+            s_item = next;
+        }
+        __syncthreads();
+        it = s_item;
     }
 }
 
@@ -128,19 +144,19 @@ hipError_t batch_grid(int dtype, size_t lds, int* grid) {
 }
 
 hipError_t launch_batch(int dtype, int grid, size_t lds, const BatchProb* probs,
-                        const int64_t* item_off, int nprob, int64_t total,
-                        const int64_t* queues, unsigned long long* counters,
-                        const int* merge_ids, const int64_t* piece_off, int nmerge,
-                        int64_t total_pieces, hipStream_t st) {
+                        const WorkItem* items, int64_t total, const int64_t* queues,
+                        unsigned long long* counters, const int* merge_ids,
+                        const int64_t* piece_off, int nmerge, int64_t total_pieces,
+                        hipStream_t st) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kWave), 0, st, counters);
     if (total > 0) {
         switch (dtype) {
         case 0: hipLaunchKernelGGL((k_batch<F32, kBatchUnroll>), dim3(grid), dim3(kBlock), lds, st,
-                                   probs, item_off, nprob, queues, counters); break;
+                                   probs, items, queues, counters); break;
         case 1: hipLaunchKernelGGL((k_batch<BF16, kBatchUnroll>), dim3(grid), dim3(kBlock), lds, st,
-                                   probs, item_off, nprob, queues, counters); break;
+                                   probs, items, queues, counters); break;
         case 2: hipLaunchKernelGGL((k_batch<F16, kBatchUnroll>), dim3(grid), dim3(kBlock), lds, st,
-                                   probs, item_off, nprob, queues, counters); break;
+                                   probs, items, queues, counters); break;
         default: return hipErrorInvalidValue;
         }
     }

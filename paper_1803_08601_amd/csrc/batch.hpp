@@ -11,6 +11,22 @@ namespace spmmk {
 constexpr int kBatchUnroll = 4;
 // One work queue per XCD.
 constexpr int kBatchQueues = 8;
+// Largest merge piece in a batch: the persistent kernel reserves the LDS of
+// its largest piece in every workgroup, so pieces stay small enough that LDS
+// does not limit occupancy below what registers allow.
+constexpr int kBatchMaxW = 1024;
+// Entries a work item aims at: several row blocks or merge pieces per item,
+// so the per-item cost of taking work from a queue stays small.
+constexpr int kBatchItemEntries = 4096;
+
+// One unit of work: `count` consecutive row blocks (row split) or merge
+// pieces of problem `prob`, column tile `coltile`.
+struct WorkItem {
+    int prob;
+    int coltile;
+    int first;
+    int count;
+};
 
 struct BatchProb {
     const int* rowptr;
@@ -28,7 +44,6 @@ struct BatchProb {
     int W;
     int col_tiles;
     int pad;
-    int64_t items;  // tiles of this problem (including column tiles)
     const int* coords;
     float* carry_vals;
     int* carry_rows;
@@ -41,9 +56,9 @@ hipError_t batch_grid(int dtype, size_t lds, int* grid);
 // queues: kBatchQueues first-item offsets followed by kBatchQueues lengths;
 // counters: kBatchQueues counters (re-armed by the launch).
 hipError_t launch_batch(int dtype, int grid, size_t lds, const BatchProb* probs,
-                        const int64_t* item_off, int nprob, int64_t total,
-                        const int64_t* queues, unsigned long long* counters,
-                        const int* merge_ids, const int64_t* piece_off, int nmerge,
-                        int64_t total_pieces, hipStream_t st);
+                        const WorkItem* items, int64_t total, const int64_t* queues,
+                        unsigned long long* counters, const int* merge_ids,
+                        const int64_t* piece_off, int nmerge, int64_t total_pieces,
+                        hipStream_t st);
 
 }  // namespace spmmk

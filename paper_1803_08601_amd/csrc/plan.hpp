@@ -69,6 +69,7 @@ int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const vo
 // candidate, and buffers of the caller to time candidates on (else scratch).
 struct TuneOpts {
     int fixed_unroll = 0;
+    int max_W = 0;  // largest merge piece allowed (0: no limit)
     const void* vals = nullptr;
     const void* B = nullptr;
     float* C = nullptr;

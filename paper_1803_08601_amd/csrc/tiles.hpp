@@ -28,9 +28,10 @@ namespace spmmk {
 //           slots), so short rows still fill the wavefront ("thread per
 //           row" granularity of Sec. 4.1 when the team is one slot) and
 //           long rows get several B rows in flight per step.
-// A team loads up to its lane count of (column, value) pairs with one
-// coalesced access per lane and broadcasts them to its slots with ds_bpermute
-// (the wave64 form of the paper's shuffle broadcast). Each slot keeps U
+// A team loads up to twice its lane count of (column, value) pairs with two
+// coalesced accesses per lane and broadcasts them to its slots with
+// ds_bpermute (the wave64 form of the paper's shuffle broadcast); the next
+// chunk of pairs is loaded while the current one is processed. Each slot keeps U
 // B-row gathers in flight before it accumulates them (the ILP of Table 1).
 // At the end of the row the team's slots are combined by a butterfly of
 // lane exchanges and the first slot writes the C row once.
@@ -68,14 +69,30 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
 
-    for (int base = p0; base < p1; base += TL) {
-        const int cnt = min(TL, p1 - base);
-        int my_c = 0;
-        float my_v = 0.f;
-        if (tl < cnt) {
-            my_c = __builtin_nontemporal_load(colind + base + tl);
-            my_v = load_elem(vals + base + tl, S{});
+    // A chunk is 2 * TL entries: lane tl holds entries tl and tl + TL. The
+    // next chunk's pairs are loaded while the current one is processed.
+    const int CH = 2 << tl_log2;
+    int cc0 = 0, cc1 = 0;
+    float cv0 = 0.f, cv1 = 0.f;
+    auto load_pair = [&](int base, int& c0, float& v0, int& c1, float& v1) {
+        const int t0 = base + tl, t1 = base + TL + tl;
+        c0 = 0; v0 = 0.f; c1 = 0; v1 = 0.f;
+        if (t0 < p1) {
+            c0 = __builtin_nontemporal_load(colind + t0);
+            v0 = load_elem(vals + t0, S{});
         }
+        if (t1 < p1) {
+            c1 = __builtin_nontemporal_load(colind + t1);
+            v1 = load_elem(vals + t1, S{});
+        }
+    };
+    if (p0 < p1) load_pair(p0, cc0, cv0, cc1, cv1);
+    for (int base = p0; base < p1; base += CH) {
+        const int cnt = min(CH, p1 - base);
+        const bool more = base + CH < p1;  // uniform within the team
+        int nc0 = 0, nc1 = 0;
+        float nv0 = 0.f, nv1 = 0.f;
+        if (more) load_pair(base + CH, nc0, nv0, nc1, nv1);
         const int nsteps = (cnt + (1 << ts_log2) - 1) >> ts_log2;
         for (int s = 0; s < nsteps; s += U) {
             int c[U];
@@ -83,11 +100,14 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
             bool ok[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = ((s + u) << ts_log2) + slot;  // entry index within the chunk
+                // entry index within the chunk; steps below G read the first
+                // pair member, the rest the second (the same for every slot)
+                const int idx = ((s + u) << ts_log2) + slot;
+                const bool second = ((s + u) >> g_log2) != 0;
                 ok[u] = idx < cnt;
                 const int src = team_base + (idx & (TL - 1));
-                c[u] = __shfl(my_c, src, kWave);
-                const float vv = __shfl(my_v, src, kWave);
+                c[u] = __shfl(second ? cc1 : cc0, src, kWave);
+                const float vv = __shfl(second ? cv1 : cv0, src, kWave);
                 v[u] = ok[u] ? vv : 0.f;
             }
             float b[U][VEC];
@@ -106,6 +126,7 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
                 for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v[u], b[u][e], acc[e]);
             }
         }
+        cc0 = nc0; cc1 = nc1; cv0 = nv0; cv1 = nv1;
     }
     // Combine the team's slots (lanes G, 2G, ... apart) by a butterfly.
     for (int off = 1 << g_log2; off < TL; off <<= 1) {
