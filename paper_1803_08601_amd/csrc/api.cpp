@@ -373,6 +373,7 @@ void destroy_plan(spmm_plan_s* p) {
     if (!p) return;
     (void)hipDeviceSynchronize();
     free_ws(p->ws);
+    free_ws(p->sddmm_ws);
     if (p->tr.at_rowptr) (void)hipFree(p->tr.at_rowptr);
     if (p->tr.at_colind) (void)hipFree(p->tr.at_colind);
     if (p->tr.perm) (void)hipFree(p->tr.perm);
@@ -427,6 +428,9 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
         p->cfg.items_per_wg = opts->max_W;
     if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_MERGE)
         rc = prepare_merge(*p, p->ws, p->cfg.items_per_wg, st);
+    // SDDMM walks merge pieces; a row-split plan gets a partition for it.
+    if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_ROWSPLIT && p->m > 0 && p->nnz > 0)
+        rc = prepare_merge(*p, p->sddmm_ws, kSddmmW, st);
     if (rc == SPMM_OK) {
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = hip_fail(e, "plan synchronise");

@@ -8,10 +8,9 @@ using namespace spmmh;
 
 namespace {
 
-// SDDMM entries per slot: enough consecutive entries to reuse the dC row
-// chunk across short rows, few enough to keep every slot busy.
-constexpr int kSddmmEntries = 16;
-constexpr int kSddmmUnroll = 4;
+// SDDMM keeps 4 entries in flight per slot, 2 with 8-wide 16-bit rows (whose
+// dC chunks take 8 registers each) so that occupancy stays at 8 waves/SIMD.
+int sddmm_unroll(int vec) { return vec == 8 ? 2 : 4; }
 
 }  // namespace
 
@@ -119,9 +118,13 @@ int spmm_sddmm(spmm_plan_t plan, const float* dC, const void* B, float* dvals, v
     if (vec != 1 && (!aligned16(dC) || !aligned16(B))) vec = 1;
     int g_log2, col_tiles;
     slot_geometry(plan->n, vec, &g_log2, &col_tiles);
-    hipError_t e = spmmk::launch_sddmm(plan->dtype, vec, kSddmmUnroll, g_log2, col_tiles,
-                                       kSddmmEntries, plan->rowptr, plan->colind, dC, B, dvals,
-                                       plan->m, plan->nnz, plan->n, plan->ld, st);
+    const bool own = plan->cfg.kernel == SPMM_KERNEL_MERGE;
+    const MergeWs& ws = own ? plan->ws : plan->sddmm_ws;
+    const int W = own ? plan->cfg.items_per_wg : kSddmmW;
+    if (!ws.coords) return fail(SPMM_ERR_STATE, "plan has no merge partition for SDDMM");
+    hipError_t e = spmmk::launch_sddmm(plan->dtype, vec, sddmm_unroll(vec), g_log2, col_tiles,
+                                       plan->rowptr, plan->colind, dC, B, dvals, plan->n,
+                                       plan->ld, ws.coords, ws.P, W, st);
     if (e != hipSuccess) return hip_fail(e, "SDDMM launch");
     return SPMM_OK;
 }

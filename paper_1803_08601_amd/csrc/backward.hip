@@ -211,98 +211,110 @@ hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int
 
 // ------------------------------------------------------------------ SDDMM
 //
-// Entries are split evenly: slot s (2^g_log2 lanes covering one column tile
-// of a row) takes entries [s E, (s+1) E), finds the row of its first entry
-// by binary search, and walks them in order, reloading its dC row chunk only
-// when the row changes. Per entry it gathers the B row chunk, forms VEC
-// partial products, loops over the column tiles, and reduces the slot's
-// lanes with DPP row exchanges; lane 0 of the slot writes dvals[p]. The split is
-// independent of row lengths, so long rows cost no more than short ones.
+// dvals[p] = <dC[row(p), :], B[colind[p], :]> on the merge pieces of the plan
+// (the Phase 1 partition of Algorithm 1), so that the work per workgroup is
+// the same whatever the row lengths: a 159k-entry row costs no more per entry
+// than a short one. A workgroup stages its piece's row ends and column indices
+// in LDS; its slots (2^g_log2 lanes covering one column tile of a row) split
+// the piece evenly with the diagonal search on the LDS copy and walk their
+// entries in order, finding each entry's row among the staged row ends. For U
+// entries at a time a slot gathers the B row chunks and the dC row chunks
+// (the latter mostly cache hits, as neighbouring entries share rows), forms
+// the partial dot products over all column tiles, and sums its lanes with DPP
+// row exchanges; lane 0 writes dvals. No entry depends on another, so there is
+// no carry-out.
 template <class S, int VEC, int U>
 __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr,
                                                    const int* __restrict__ colind,
                                                    const float* __restrict__ dC,
                                                    const typename S::T* __restrict__ B,
-                                                   float* __restrict__ dvals, int64_t m,
-                                                   int64_t nnz, int n, int64_t ld, int g_log2,
-                                                   int col_tiles, int E) {
+                                                   float* __restrict__ dvals, int n, int64_t ld,
+                                                   int g_log2, int col_tiles,
+                                                   const int* __restrict__ coords, int W) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int* s_col = reinterpret_cast<int*>(smem);  // [W]
+    int* s_rowend = s_col + W;                  // [W] local row ends
+    const int tile = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int i0 = coords[2 * tile], j0 = coords[2 * tile + 1];
+    const int i1 = coords[2 * tile + 2], j1 = coords[2 * tile + 3];
+    const int nr = i1 - i0, nj = j1 - j0;
+    for (int t = threadIdx.x; t < nr; t += kBlock)
+        s_rowend[t] = __builtin_nontemporal_load(rowptr + i0 + 1 + t) - j0;
+    for (int t = threadIdx.x; t < nj; t += kBlock) s_col[t] = __builtin_nontemporal_load(colind + j0 + t);
+    __syncthreads();
+
     const int G = 1 << g_log2;
+    const int NS = kBlock >> g_log2;
+    const int slot = threadIdx.x >> g_log2;
     const int g = threadIdx.x & (G - 1);
-    const int64_t slot = ((int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> g_log2;
-    const int64_t p0 = slot * E;
-    if (p0 >= nnz) return;  // whole slot leaves together (E and G fixed per slot)
-    const int64_t p1 = p0 + E < nnz ? p0 + E : nnz;
-    int64_t lo = 0, hi = m - 1;  // last row with rowptr[row] <= p0
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (rowptr[mid] <= p0) lo = mid; else hi = mid - 1;
-    }
-    int64_t row = lo;
-    int64_t row_end = rowptr[row + 1];
+    const int items = nr + nj;
+    const int ips = (items + NS - 1) / NS;
+    const int d0 = min(slot * ips, items), d1 = min(d0 + ips, items);
+    auto search = [&](int d) {
+        int lo = max(0, d - nj), hi = min(d, nr);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_rowend[mid] + mid < d) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    int r = search(d0);
+    const int js = d0 - r;
+    const int je = d1 - search(d1);
     const int span = VEC << g_log2;
-    for (int64_t pb = p0; pb < p1; pb += U) {
+    for (int jb = js; jb < je; jb += U) {
+        int rr[U], c[U];
         float part[U];
-        int c[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            const int j = jb + u;
+            if (j < je) {
+                while (r < nr && s_rowend[r] <= j) ++r;  // rows that end before entry j
+                c[u] = s_col[j];
+            } else {
+                c[u] = 0;
+            }
+            rr[u] = r;
             part[u] = 0.f;
-            c[u] = pb + u < p1 ? __builtin_nontemporal_load(colind + pb + u) : 0;
         }
         for (int t = 0; t < col_tiles; ++t) {
             const int col = t * span + g * VEC;
             const bool col_ok = col < n;
-            float b[U][VEC];
+            float b[U][VEC], d[U][VEC];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (pb + u < p1 && col_ok) {
+                if (jb + u < je && col_ok) {
                     load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
+                    load_f32<VEC>(dC + (int64_t)(i0 + rr[u]) * ld + col, d[u]);
                 } else {
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
+                    for (int e = 0; e < VEC; ++e) b[u][e] = d[u][e] = 0.f;
                 }
             }
-            int64_t r = row, re = row_end;
-            float d[VEC];
-            bool have = false;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t p = pb + u;
-                if (p < p1) {
-                    bool moved = false;
-                    while (re <= p) { ++r; re = rowptr[r + 1]; moved = true; }
-                    if (!have || moved) {
-                        if (col_ok) load_f32<VEC>(dC + r * ld + col, d);
-                        else {
 #pragma unroll
-                            for (int e = 0; e < VEC; ++e) d[e] = 0.f;
-                        }
-                        have = true;
-                    }
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) part[u] = fmaf(d[e], b[u][e], part[u]);
-                }
+                for (int e = 0; e < VEC; ++e) part[u] = fmaf(d[u][e], b[u][e], part[u]);
             }
-            if (t == col_tiles - 1) { row = r; row_end = re; }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             part[u] = group_sum(part[u], g_log2);
-            if (g == 0 && pb + u < p1) __builtin_nontemporal_store(part[u], dvals + pb + u);
+            if (g == 0 && jb + u < je) __builtin_nontemporal_store(part[u], dvals + j0 + jb + u);
         }
     }
 }
 
 template <class S, int VEC>
-static hipError_t sddmm_go(int unroll, int g_log2, int col_tiles, int E, const int* rowptr,
+static hipError_t sddmm_go(int unroll, int g_log2, int col_tiles, const int* rowptr,
                            const int* colind, const float* dC, const void* B, float* dvals,
-                           int64_t m, int64_t nnz, int64_t n, int64_t ld, hipStream_t st) {
-    const int64_t slots = (nnz + E - 1) / E;
-    const int64_t threads = slots << g_log2;
-    const uint32_t grid = (uint32_t)((threads + kBlock - 1) / kBlock);
+                           int64_t n, int64_t ld, const int* coords, int64_t P, int W,
+                           hipStream_t st) {
+    const size_t lds = sizeof(int) * 2 * (size_t)W;
     const typename S::T* Bp = static_cast<const typename S::T*>(B);
-#define SDDMM_LAUNCH(UU)                                                                        \
-    hipLaunchKernelGGL((k_sddmm<S, VEC, UU>), dim3(grid), dim3(kBlock), 0, st, rowptr, colind, \
-                       dC, Bp, dvals, m, nnz, (int)n, ld, g_log2, col_tiles, E)
+#define SDDMM_LAUNCH(UU)                                                                         \
+    hipLaunchKernelGGL((k_sddmm<S, VEC, UU>), dim3((uint32_t)P), dim3(kBlock), lds, st, rowptr, \
+                       colind, dC, Bp, dvals, (int)n, ld, g_log2, col_tiles, coords, W)
     switch (unroll) {
     case 1: SDDMM_LAUNCH(1); break;
     case 2: SDDMM_LAUNCH(2); break;
@@ -314,22 +326,21 @@ static hipError_t sddmm_go(int unroll, int g_log2, int col_tiles, int E, const i
     return hipGetLastError();
 }
 
-hipError_t launch_sddmm(int dtype, int vec, int unroll, int g_log2, int col_tiles, int E,
+hipError_t launch_sddmm(int dtype, int vec, int unroll, int g_log2, int col_tiles,
                         const int* rowptr, const int* colind, const float* dC, const void* B,
-                        float* dvals, int64_t m, int64_t nnz, int64_t n, int64_t ld,
+                        float* dvals, int64_t n, int64_t ld, const int* coords, int64_t P, int W,
                         hipStream_t st) {
-    if (nnz <= 0 || m <= 0) return hipSuccess;
-    if ((((nnz + E - 1) / E) << g_log2) >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+    if (P <= 0) return hipSuccess;
     switch (dtype) {
     case 0:
-        if (vec == 4) return sddmm_go<F32, 4>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
-        return sddmm_go<F32, 1>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
+        if (vec == 4) return sddmm_go<F32, 4>(unroll, g_log2, col_tiles, rowptr, colind, dC, B, dvals, n, ld, coords, P, W, st);
+        return sddmm_go<F32, 1>(unroll, g_log2, col_tiles, rowptr, colind, dC, B, dvals, n, ld, coords, P, W, st);
     case 1:
-        if (vec == 8) return sddmm_go<BF16, 8>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
-        return sddmm_go<BF16, 1>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
+        if (vec == 8) return sddmm_go<BF16, 8>(unroll, g_log2, col_tiles, rowptr, colind, dC, B, dvals, n, ld, coords, P, W, st);
+        return sddmm_go<BF16, 1>(unroll, g_log2, col_tiles, rowptr, colind, dC, B, dvals, n, ld, coords, P, W, st);
     case 2:
-        if (vec == 8) return sddmm_go<F16, 8>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
-        return sddmm_go<F16, 1>(unroll, g_log2, col_tiles, E, rowptr, colind, dC, B, dvals, m, nnz, n, ld, st);
+        if (vec == 8) return sddmm_go<F16, 8>(unroll, g_log2, col_tiles, rowptr, colind, dC, B, dvals, n, ld, coords, P, W, st);
+        return sddmm_go<F16, 1>(unroll, g_log2, col_tiles, rowptr, colind, dC, B, dvals, n, ld, coords, P, W, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -59,10 +59,11 @@ int64_t transpose_hist_len(int64_t nnz);
 hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int64_t n,
                                float* out, hipStream_t st);
 
-// dvals[p] = <dC[row(p), :n], B[colind[p], :n]>, E entries per slot.
-hipError_t launch_sddmm(int dtype, int vec, int unroll, int g_log2, int col_tiles, int E,
+// dvals[p] = <dC[row(p), :n], B[colind[p], :n]> over the P merge pieces of W
+// items given by coords (2 * (P + 1) ints).
+hipError_t launch_sddmm(int dtype, int vec, int unroll, int g_log2, int col_tiles,
                         const int* rowptr, const int* colind, const float* dC, const void* B,
-                        float* dvals, int64_t m, int64_t nnz, int64_t n, int64_t ld,
+                        float* dvals, int64_t n, int64_t ld, const int* coords, int64_t P, int W,
                         hipStream_t st);
 
 }  // namespace spmmk

@@ -50,11 +50,16 @@ struct spmm_plan_s {
     double tuned_ms = 0.0;
     int device = 0;
     spmmh::MergeWs ws;
+    spmmh::MergeWs sddmm_ws;  // merge partition for SDDMM when the kernel is row split
     spmmh::Transpose tr;
     spmm_plan_s* tplan = nullptr;  // plan over A^T (k rows, m columns)
 };
 
 namespace spmmh {
+
+// Merge items per workgroup of the SDDMM kernel when the plan has no merge
+// partition of its own.
+constexpr int kSddmmW = 2048;
 
 bool plan_alive(const spmm_plan_s* p);
 bool aligned16(const void* ptr);
