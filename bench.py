@@ -120,8 +120,13 @@ def gcn_fwd_bwd(steps=20, warmup=3):
     for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
         vals = torch.from_numpy(A.vals.astype(np.float32)).to(dt).cuda()
         Bt = torch.from_numpy(B).to(dt).cuda()
+        sv = torch.tensor([], dtype=dt).element_size()
         plan = nv.Plan(rp, ci, A.m, A.k, n, dtype=nv.dtype_code(dt), mode="autotune", nnz=A.nnz)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         plan.transpose_build()
+        torch.cuda.synchronize()
+        tr_ms = (time.perf_counter() - t0) * 1e3
         C = torch.empty(A.m, n, device="cuda")
         dB = torch.empty(A.k, n, device="cuda")
         dv = torch.empty(A.nnz, device="cuda")
@@ -134,9 +139,18 @@ def gcn_fwd_bwd(steps=20, warmup=3):
             plan.execute_t(vals, dC, dB)
             plan.sddmm(dC, Bt, dv)
         total = _timed(step, steps, warmup)
+        # compulsory bytes of each product (A, the dense inputs and outputs once)
+        b_fwd = bytes_min(A.m, A.k, A.nnz, n, sv, sv)
+        b_db = 4 * (A.k + 1) + (4 + 4) * A.nnz + (4 + 4 + sv) * A.nnz + 4 * A.m * n + 4 * A.k * n
+        b_dv = 4 * (A.m + 1) + 4 * A.nnz + 4 * A.m * n + sv * A.k * n + 4 * A.nnz
+
+        def gbs(b, ms_):
+            return round(b / (ms_ * 1e-3) / 1e9, 1)
         out[name] = {"fwd_ms": round(fwd, 4), "dB_ms": round(bwd_b, 4), "dvals_ms": round(bwd_v, 4),
-                     "fwd_bwd_ms": round(total, 4),
+                     "fwd_bwd_ms": round(total, 4), "transpose_build_ms": round(tr_ms, 2),
                      "fwd_gflops": round(2.0 * A.nnz * n / (fwd * 1e-3) / 1e9, 1),
+                     "algorithmic_GBs": {"fwd": gbs(b_fwd, fwd), "dB": gbs(b_db, bwd_b),
+                                         "dvals": gbs(b_dv, bwd_v)},
                      "kernel": "merge" if plan.info().config.kernel else "rowsplit"}
         plan.close()
     out["bf16_speedup_fwd_bwd"] = round(out["f32"]["fwd_bwd_ms"] / out["bf16"]["fwd_bwd_ms"], 3)
@@ -177,7 +191,10 @@ def batched(steps=10, warmup=2):
         ms = _timed(lambda: nv.spmm_batch_run(h), steps, warmup)
         cfgs = [nv.spmm_batch_problem_config(h, b) for b in range(len(probs))]
         nv.spmm_batch_destroy(h)
+        sv = torch.tensor([], dtype=dt).element_size()
+        bmin = sum(bytes_min(P.A.m, P.A.k, P.A.nnz, P.n, sv, sv) for P in probs)
         rec = {"graph_ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+               "algorithmic_GBs": round(bmin / (ms * 1e-3) / 1e9, 1),
                "plan_s": round(plan_s, 2), "merge_problems": int(sum(c.kernel for c in cfgs))}
         if name == "f32":
             # the plain kernel called once per problem: with the batch's own
