@@ -75,6 +75,14 @@ typedef enum spmm_mode {
 
 typedef enum spmm_kernel { SPMM_KERNEL_ROWSPLIT = 0, SPMM_KERNEL_MERGE = 1 } spmm_kernel;
 
+/* Semirings of spmm_execute_semiring: (add, multiply, identity). */
+typedef enum spmm_semiring {
+    SPMM_PLUS_TIMES = 0, /* (+, *, 0): the ordinary product */
+    SPMM_MIN_PLUS = 1,   /* (min, +, +inf): shortest-path relaxation */
+    SPMM_MAX_PLUS = 2,   /* (max, +, -inf) */
+    SPMM_MAX_TIMES = 3   /* (max, *, -inf) */
+} spmm_semiring;
+
 /* Kernel shape. A zero field means "choose automatically". */
 typedef struct spmm_config {
     int32_t kernel;        /* spmm_kernel */
@@ -152,6 +160,16 @@ int spmm_execute(spmm_plan_t plan, const void* A_vals, const void* B, float* C, 
  * ev_after), so their elapsed time is that kernel's duration. */
 int spmm_execute_events(spmm_plan_t plan, const void* A_vals, const void* B, float* C,
                         void* ev_before, void* ev_after, void* stream);
+
+/* C[i,c] = (add) over the entries p of row i of (A_vals[p] (multiply)
+ * B[colind[p], c]) for one of the semirings above - SpMM as an instance of
+ * the GraphBLAS product on a semiring (Sec. 1). Same plan, kernels and
+ * launch shape as spmm_execute; rows without entries give the identity.
+ * min and max are exact, so results do not depend on the summation order:
+ * each element is the float32 rounding of the exact result whenever every
+ * product or sum of two stored values is exact in float64. Enqueue only. */
+int spmm_execute_semiring(spmm_plan_t plan, int32_t semiring, const void* A_vals, const void* B,
+                          float* C, void* stream);
 
 /* Plan facts for the host (sizes, the chosen config, Sec. 5.4 choice). */
 int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info_host);

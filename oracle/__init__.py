@@ -41,6 +41,8 @@ def lib():
                                     i64, dp, ctypes.c_int]
         L.oracle_sddmm.argtypes = [i64, i64, i32p, i32p, vp, ctypes.c_int, i64, vp, ctypes.c_int,
                                    i64, dp, ctypes.c_int, ctypes.c_int]
+        L.oracle_spmm_semiring.argtypes = [i64, i64, i32p, i32p, vp, ctypes.c_int, vp, ctypes.c_int,
+                                           i64, dp, i64, ctypes.c_int]
         L.oracle_transpose.argtypes = [i64, i64, i32p, i32p, i32p, i32p, i32p]
         L.oracle_merge_walk.argtypes = [i64, i32p, i32p]
         L.oracle_merge_search.argtypes = [i64, i32p, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -110,6 +112,24 @@ def spmm_rows(rowptr, colind, vals, B, rows, n=None, vals_tag=None, b_tag=None, 
                                 rows.shape[0], _p(out), int(absval), nthreads)
     assert rc == 0
     return out
+
+
+PLUS_TIMES, MIN_PLUS, MAX_PLUS, MAX_TIMES = 0, 1, 2, 3
+
+
+def spmm_semiring(rowptr, colind, vals, B, semiring, n=None, vals_tag=None, b_tag=None):
+    """C = A (+).(x) B over a semiring (codes above), FP64, m-by-n."""
+    rowptr, colind = _csr(rowptr, colind)
+    vals, vt = _tagged(vals, vals_tag)
+    B, bt = _tagged(B, b_tag)
+    m = rowptr.shape[0] - 1
+    ld = B.shape[1]
+    n = ld if n is None else n
+    C = np.empty((m, n), dtype=np.float64)
+    rc = lib().oracle_spmm_semiring(m, n, _p(rowptr), _p(colind), _p(vals), vt, _p(B), bt, ld,
+                                    _p(C), n, semiring)
+    assert rc == 0
+    return C
 
 
 def spmm_t(rowptr, colind, vals, dC, k, n=None, vals_tag=None, c_tag=None, absval=False):

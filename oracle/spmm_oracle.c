@@ -130,6 +130,39 @@ int oracle_spmm_rows(int64_t n, const int32_t* rowptr, const int32_t* colind, co
     return 0;
 }
 
+/* Product over a semiring (Sec. 1: SpMM as an instance of the GraphBLAS
+ * matrix product on a semiring): C[i,c] = (+)_{p in row i} vals[p] (x)
+ * B[colind[p], c], with (+, x, identity) one of
+ *   0: (+, *, 0)          the ordinary product
+ *   1: (min, +, +inf)     shortest-path relaxation
+ *   2: (max, +, -inf)
+ *   3: (max, *, -inf)
+ * Rows without entries give the identity. */
+int oracle_spmm_semiring(int64_t m, int64_t n, const int32_t* rowptr, const int32_t* colind,
+                         const void* vals, int vdt, const void* B, int bdt, int64_t ldb,
+                         double* C, int64_t ldc, int semiring) {
+    if (m < 0 || n < 0 || ldb < n || ldc < n || semiring < 0 || semiring > 3) return -1;
+    const double ident = semiring == 0 ? 0.0 : semiring == 1 ? INFINITY : -INFINITY;
+    for (int64_t i = 0; i < m; ++i) {
+        double* out = C + i * ldc;
+        for (int64_t c = 0; c < n; ++c) out[c] = ident;
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            double a = or_load(vals, p, vdt);
+            int64_t r = colind[p];
+            for (int64_t c = 0; c < n; ++c) {
+                double b = or_load(B, r * ldb + c, bdt);
+                switch (semiring) {
+                case 0: out[c] += a * b; break;
+                case 1: out[c] = fmin(out[c], a + b); break;
+                case 2: out[c] = fmax(out[c], a + b); break;
+                default: out[c] = fmax(out[c], a * b); break;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
 /* dB (k-by-n, doubles, row stride n) = A^T * dC, accumulated by scattering
  * each row of A in CSR order: dB[colind[p], :] += vals[p] * dC[i, :]. */
 int oracle_spmm_t(int64_t m, int64_t k, int64_t n, const int32_t* rowptr, const int32_t* colind,

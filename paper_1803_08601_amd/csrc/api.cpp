@@ -91,26 +91,22 @@ static size_t lds_limit() {
 }
 
 int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const void* vals,
-            const void* B, float* C, hipStream_t st, hipEvent_t ev_before, hipEvent_t ev_after) {
+            const void* B, float* C, hipStream_t st, hipEvent_t ev_before, hipEvent_t ev_after,
+            int semiring) {
     if (p.m == 0 || p.n == 0) return SPMM_OK;
     int vec = p.cfg.vec;
     if (vec != 1 && (!aligned16(B) || !aligned16(C))) vec = 1;
     const spmmk::Shape s = resolve_shape(p, vec);
-    hipError_t e;
+    const bool merge = p.cfg.kernel == SPMM_KERNEL_MERGE;
+    if (merge && !p.ws.coords) return fail(SPMM_ERR_STATE, "merge plan without partition");
+    const spmmk::ForwardArgs a{rowptr, colind, vals, B, C, p.m, p.n, p.ld,
+                               p.ws.coords, p.ws.P, p.ws.carry_vals, p.ws.carry_rows};
     if (ev_before) SPMM_HIP(hipEventRecord(ev_before, st));
-    if (p.cfg.kernel == SPMM_KERNEL_ROWSPLIT) {
-        e = spmmk::launch_rowsplit(p.dtype, s, rowptr, colind, vals, B, C, p.m, p.n, p.ld, st);
-        if (e != hipSuccess) return hip_fail(e, "row-split launch");
-        if (ev_after) SPMM_HIP(hipEventRecord(ev_after, st));
-    } else {
-        if (!p.ws.coords) return fail(SPMM_ERR_STATE, "merge plan without partition");
-        e = spmmk::launch_merge(p.dtype, s, rowptr, colind, vals, B, C, p.m, p.n, p.ld,
-                                p.ws.coords, p.ws.P, p.ws.carry_vals, p.ws.carry_rows, st);
-        if (e != hipSuccess) return hip_fail(e, "merge launch");
-        if (ev_after) SPMM_HIP(hipEventRecord(ev_after, st));
-        e = spmmk::launch_merge_fixup(C, p.ld, p.n, p.ws.carry_vals, p.ws.carry_rows, p.ws.P, st);
-        if (e != hipSuccess) return hip_fail(e, "merge fix-up launch");
-    }
+    const hipError_t e =
+        semiring == SPMM_PLUS_TIMES
+            ? spmmk::launch_forward_plus_times(p.dtype, merge, s, a, st, ev_after)
+            : spmmk::launch_forward_semiring(semiring, p.dtype, merge, s, a, st);
+    if (e != hipSuccess) return hip_fail(e, merge ? "merge-based launch" : "row-split launch");
     return SPMM_OK;
 }
 
@@ -510,6 +506,18 @@ int spmm_execute_events(spmm_plan_t plan, const void* A_vals, const void* B, flo
     return forward(*plan, plan->rowptr, plan->colind, A_vals, B, C,
                    static_cast<hipStream_t>(stream), static_cast<hipEvent_t>(ev_before),
                    static_cast<hipEvent_t>(ev_after));
+}
+
+int spmm_execute_semiring(spmm_plan_t plan, int32_t semiring, const void* A_vals, const void* B,
+                          float* C, void* stream) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (semiring < SPMM_PLUS_TIMES || semiring > SPMM_MAX_TIMES)
+        return fail(SPMM_ERR_INVALID, "semiring %d", semiring);
+    if (plan->m == 0 || plan->n == 0) return SPMM_OK;
+    if (!C) return fail(SPMM_ERR_INVALID, "C is NULL");
+    if (plan->nnz > 0 && (!A_vals || !B)) return fail(SPMM_ERR_INVALID, "A_vals or B is NULL");
+    return forward(*plan, plan->rowptr, plan->colind, A_vals, B, C,
+                   static_cast<hipStream_t>(stream), nullptr, nullptr, semiring);
 }
 
 int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info) {

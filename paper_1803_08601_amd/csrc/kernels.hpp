@@ -22,20 +22,31 @@ struct Shape {
     int col_tiles = 1;
 };
 
-hipError_t launch_rowsplit(int dtype, const Shape& s, const int* rowptr, const int* colind,
-                           const void* vals, const void* B, float* C, int64_t m, int64_t n,
-                           int64_t ld, hipStream_t st);
+// Operands of one forward product; coords, P and the carry arrays are the
+// merge-based workspace (unused by row split).
+struct ForwardArgs {
+    const int* rowptr;
+    const int* colind;
+    const void* vals;
+    const void* B;
+    float* C;
+    int64_t m, n, ld;
+    const int* coords;
+    int64_t P;
+    float* carry_vals;
+    int* carry_rows;
+};
+
+// The main kernel of one product and, for merge-based plans, its fix-up pass;
+// ev_after (may be null) is recorded between the two.
+hipError_t launch_forward_plus_times(int dtype, bool merge, const Shape& s,
+                                     const ForwardArgs& a, hipStream_t st, hipEvent_t ev_after);
+// The same over semiring 1 (min, +), 2 (max, +) or 3 (max, *).
+hipError_t launch_forward_semiring(int semiring, int dtype, bool merge, const Shape& s,
+                                   const ForwardArgs& a, hipStream_t st);
 
 hipError_t launch_merge_partition(const int* rowptr, int64_t m, int64_t nnz, int W, int64_t P,
                                   int* coords, hipStream_t st);
-
-hipError_t launch_merge(int dtype, const Shape& s, const int* rowptr, const int* colind,
-                        const void* vals, const void* B, float* C, int64_t m, int64_t n,
-                        int64_t ld, const int* coords, int64_t P, float* carry_vals,
-                        int* carry_rows, hipStream_t st);
-
-hipError_t launch_merge_fixup(float* C, int64_t ld, int64_t n, const float* carry_vals,
-                              const int* carry_rows, int64_t P, hipStream_t st);
 
 // stats[0] = longest row, stats[1] = rows with >= 1024 entries,
 // stats[2] = 1 if rowptr is non-decreasing with rowptr[0] == 0 else 0.

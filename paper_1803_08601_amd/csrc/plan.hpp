@@ -69,7 +69,7 @@ int vec16(int dtype);
 spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec);
 int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const void* vals,
             const void* B, float* C, hipStream_t st, hipEvent_t ev_before = nullptr,
-            hipEvent_t ev_after = nullptr);
+            hipEvent_t ev_after = nullptr, int semiring = SPMM_PLUS_TIMES);
 // Options of plan creation used inside the library: a fixed unroll for every
 // candidate, and buffers of the caller to time candidates on (else scratch).
 struct TuneOpts {

@@ -9,6 +9,37 @@
 
 namespace spmmk {
 
+// ---------------------------------------------------------------- semirings
+// The product over a semiring (Sec. 1 names SpMM as one instance of the
+// GraphBLAS matrix product on a semiring): acc = acc (+) (v (x) b), partial
+// results combined with (+), rows without entries give the identity. The
+// ordinary product is PlusTimes (fused multiply-add). Entries a lane skips
+// must leave acc unchanged: PlusTimes feeds them as 0 * 0, the others skip.
+struct PlusTimes {
+    static constexpr bool kZeroTermIsNeutral = true;
+    __device__ static float zero() { return 0.f; }
+    __device__ static float mac(float acc, float v, float b) { return fmaf(v, b, acc); }
+    __device__ static float add(float x, float y) { return x + y; }
+};
+struct MinPlus {
+    static constexpr bool kZeroTermIsNeutral = false;
+    __device__ static float zero() { return __builtin_inff(); }
+    __device__ static float mac(float acc, float v, float b) { return fminf(acc, v + b); }
+    __device__ static float add(float x, float y) { return fminf(x, y); }
+};
+struct MaxPlus {
+    static constexpr bool kZeroTermIsNeutral = false;
+    __device__ static float zero() { return -__builtin_inff(); }
+    __device__ static float mac(float acc, float v, float b) { return fmaxf(acc, v + b); }
+    __device__ static float add(float x, float y) { return fmaxf(x, y); }
+};
+struct MaxTimes {
+    static constexpr bool kZeroTermIsNeutral = false;
+    __device__ static float zero() { return -__builtin_inff(); }
+    __device__ static float mac(float acc, float v, float b) { return fmaxf(acc, v * b); }
+    __device__ static float add(float x, float y) { return fmaxf(x, y); }
+};
+
 // ---------------------------------------------------------------- row split
 // Row-split SpMM (paper Sec. 4.1, Fig. 3) for gfx950 wavefronts.
 //
@@ -41,7 +72,7 @@ namespace spmmk {
 
 // One workgroup's rows of the row-split product (rows blk * R .. blk * R + R - 1
 // with R = rows per workgroup) for column tile `coltile`.
-template <class S, int VEC, int U>
+template <class S, int VEC, int U, class R = PlusTimes>
 __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
                                                const int* __restrict__ colind,
                                                const typename S::T* __restrict__ vals,
@@ -67,7 +98,7 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
     }
     float acc[VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+    for (int e = 0; e < VEC; ++e) acc[e] = R::zero();
 
     // A chunk is 2 * TL entries: lane tl holds entries tl and tl + TL. The
     // next chunk's pairs are loaded while the current one is processed.
@@ -122,8 +153,10 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                if (R::kZeroTermIsNeutral || ok[u]) {
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v[u], b[u][e], acc[e]);
+                    for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
+                }
             }
         }
         cc0 = nc0; cc1 = nc1; cv0 = nv0; cv1 = nv1;
@@ -131,7 +164,7 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
     // Combine the team's slots (lanes G, 2G, ... apart) by a butterfly.
     for (int off = 1 << g_log2; off < TL; off <<= 1) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] += __shfl_xor(acc[e], off, kWave);
+        for (int e = 0; e < VEC; ++e) acc[e] = R::add(acc[e], __shfl_xor(acc[e], off, kWave));
     }
     if (slot == 0 && row < m && col_ok) store_out<VEC>(C + row * ld + col, acc);
 }
@@ -170,7 +203,7 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
 // Phase 2 for merge piece `tile` and column tile `coltile`; smem holds
 // merge_lds_bytes() of LDS. Contains workgroup barriers: every thread of the
 // workgroup must call it with the same arguments.
-template <class S, int VEC, int U>
+template <class S, int VEC, int U, class R = PlusTimes>
 __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
                                            const int* __restrict__ colind,
                                            const typename S::T* __restrict__ vals,
@@ -226,7 +259,7 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
 
     float acc[VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+    for (int e = 0; e < VEC; ++e) acc[e] = R::zero();
     int r = rs;
     int rend = r < nr ? s_rowend[r] : INT_MAX;
     auto emit = [&]() {
@@ -237,7 +270,7 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
             store_out<VEC>(C + (int64_t)(i0 + r) * ld + col, acc);
         }
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] = 0.f;
+        for (int e = 0; e < VEC; ++e) acc[e] = R::zero();
         ++r;
         rend = r < nr ? s_rowend[r] : INT_MAX;
     };
@@ -267,7 +300,7 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
             if (j < je) {
                 while (rend <= j) emit();
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v[u], b[u][e], acc[e]);
+                for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
             }
         }
     }
@@ -284,17 +317,17 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
         while (s0 > 0 && s_carry_row[s0 - 1] == h) --s0;
         float tot[VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) tot[e] = 0.f;
+        for (int e = 0; e < VEC; ++e) tot[e] = R::zero();
         for (int q = s0; q < slot; ++q) {
             float t[VEC];
             load_f32<VEC>(s_carry + (q * G + g) * VEC, t);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) tot[e] += t[e];
+            for (int e = 0; e < VEC; ++e) tot[e] = R::add(tot[e], t[e]);
         }
         float hv[VEC];
         load_f32<VEC>(s_head + threadIdx.x * VEC, hv);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) tot[e] += hv[e];
+        for (int e = 0; e < VEC; ++e) tot[e] = R::add(tot[e], hv[e]);
         store_out<VEC>(C + (int64_t)(i0 + h) * ld + col, tot);
     }
 
@@ -311,12 +344,12 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
             while (s0 > 0 && s_carry_row[s0 - 1] == nr) --s0;
             float tot[VEC];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) tot[e] = 0.f;
+            for (int e = 0; e < VEC; ++e) tot[e] = R::zero();
             for (int q = s0; q < NS; ++q) {
                 float t[VEC];
                 load_f32<VEC>(s_carry + (q * G + g) * VEC, t);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) tot[e] += t[e];
+                for (int e = 0; e < VEC; ++e) tot[e] = R::add(tot[e], t[e]);
             }
             store_f32<VEC>(carry_vals + (int64_t)tile * n + col, tot);
         }
@@ -327,6 +360,7 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
 // Phase 3 for piece p: the first piece of every run of pieces that carry
 // into the same row adds the run's carry-outs (in piece order) to that row of
 // C. One wavefront.
+template <class R = PlusTimes>
 __device__ __forceinline__ void merge_fixup_piece(float* __restrict__ C, int64_t ld, int n,
                                                   const float* __restrict__ carry_vals,
                                                   const int* __restrict__ carry_rows, int64_t P,
@@ -337,10 +371,116 @@ __device__ __forceinline__ void merge_fixup_piece(float* __restrict__ C, int64_t
     int64_t q_end = p + 1;
     while (q_end < P && carry_rows[q_end] == r) ++q_end;
     for (int c = threadIdx.x; c < n; c += kWave) {
-        float s = 0.f;
-        for (int64_t q = p; q < q_end; ++q) s += carry_vals[q * n + c];
-        C[(int64_t)r * ld + c] += s;
+        float s = R::zero();
+        for (int64_t q = p; q < q_end; ++q) s = R::add(s, carry_vals[q * n + c]);
+        C[(int64_t)r * ld + c] = R::add(C[(int64_t)r * ld + c], s);
     }
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <class S, int VEC, int U, class R>
+__global__ __launch_bounds__(kBlock) void k_rowsplit(const int* __restrict__ rowptr,
+                                                      const int* __restrict__ colind,
+                                                      const typename S::T* __restrict__ vals,
+                                                      const typename S::T* __restrict__ B,
+                                                      float* __restrict__ C, int64_t m, int n,
+                                                      int64_t ld, int g_log2, int ts_log2) {
+    const int rpb_log2 = (6 - g_log2 - ts_log2) + 2;
+    const int64_t nblk = (m + (int64_t(1) << rpb_log2) - 1) >> rpb_log2;
+    for (int64_t blk = xcd_remap(blockIdx.x, gridDim.x); blk < nblk; blk += gridDim.x)
+        rowsplit_block<S, VEC, U, R>(rowptr, colind, vals, B, C, m, n, ld, g_log2, ts_log2, blk,
+                                     blockIdx.y);
+}
+
+template <class S, int VEC, int U, class R>
+__global__ __launch_bounds__(kBlock) void k_merge(const int* __restrict__ rowptr,
+                                                   const int* __restrict__ colind,
+                                                   const typename S::T* __restrict__ vals,
+                                                   const typename S::T* __restrict__ B,
+                                                   float* __restrict__ C, int m, int n, int64_t ld,
+                                                   int g_log2, const int* __restrict__ coords,
+                                                   int W, float* __restrict__ carry_vals,
+                                                   int* __restrict__ carry_rows) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    merge_tile<S, VEC, U, R>(rowptr, colind, vals, B, C, m, n, ld, g_log2, coords, W, carry_vals,
+                             carry_rows, (int)xcd_remap(blockIdx.x, gridDim.x), blockIdx.y, smem);
+}
+
+template <class R>
+__global__ __launch_bounds__(kWave) void k_merge_fixup(float* __restrict__ C, int64_t ld, int n,
+                                                        const float* __restrict__ carry_vals,
+                                                        const int* __restrict__ carry_rows,
+                                                        int64_t P) {
+    merge_fixup_piece<R>(C, ld, n, carry_vals, carry_rows, P, blockIdx.x);
+}
+
+// Host-side dispatch over storage type, vector width and unroll for one
+// semiring (instantiated in the translation unit that owns the semiring).
+template <class S, int VEC, int U, class R>
+hipError_t launch_one(bool merge, const Shape& s, const ForwardArgs& a, hipStream_t st) {
+    const typename S::T* vals = static_cast<const typename S::T*>(a.vals);
+    const typename S::T* B = static_cast<const typename S::T*>(a.B);
+    if (!merge) {
+        const int tl_log2 = s.g_log2 + s.ts_log2;
+        const int64_t rows_per_block = int64_t(kWave >> tl_log2) * (kBlock / kWave);
+        const int64_t need = (a.m + rows_per_block - 1) / rows_per_block;
+        const uint32_t grid = (uint32_t)(need < (1 << 22) ? need : (1 << 22));
+        hipLaunchKernelGGL((k_rowsplit<S, VEC, U, R>), dim3(grid, s.col_tiles), dim3(kBlock), 0,
+                           st, a.rowptr, a.colind, vals, B, a.C, a.m, (int)a.n, a.ld, s.g_log2,
+                           s.ts_log2);
+    } else {
+        hipLaunchKernelGGL((k_merge<S, VEC, U, R>), dim3((uint32_t)a.P, s.col_tiles), dim3(kBlock),
+                           merge_lds_bytes(0, s), st, a.rowptr, a.colind, vals, B, a.C, (int)a.m,
+                           (int)a.n, a.ld, s.g_log2, a.coords, s.W, a.carry_vals, a.carry_rows);
+    }
+    return hipGetLastError();
+}
+
+template <class S, int VEC, class R>
+hipError_t launch_u(bool merge, const Shape& s, const ForwardArgs& a, hipStream_t st) {
+    switch (s.unroll) {
+    case 1: return launch_one<S, VEC, 1, R>(merge, s, a, st);
+    case 2: return launch_one<S, VEC, 2, R>(merge, s, a, st);
+    case 4: return launch_one<S, VEC, 4, R>(merge, s, a, st);
+    case 8: return launch_one<S, VEC, 8, R>(merge, s, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class S, class R>
+hipError_t launch_v(bool merge, const Shape& s, const ForwardArgs& a, hipStream_t st) {
+    if (s.vec == S::kVec16) return launch_u<S, S::kVec16, R>(merge, s, a, st);
+    if (s.vec == 1) return launch_u<S, 1, R>(merge, s, a, st);
+    return hipErrorInvalidValue;
+}
+
+// The main kernel of one product (row split, or Phase 2 of the merge-based
+// kernel) followed, for merge-based plans, by its Phase 3 fix-up.
+template <class R>
+hipError_t launch_forward(int dtype, bool merge, const Shape& s, const ForwardArgs& a,
+                          hipStream_t st, hipEvent_t ev_after) {
+    if (merge && a.P <= 0) return hipSuccess;
+    if (s.g_log2 < 0 || s.ts_log2 < 0 || s.g_log2 + s.ts_log2 > 6 || s.W < 1)
+        return hipErrorInvalidValue;
+    hipError_t e;
+    switch (dtype) {
+    case 0: e = launch_v<F32, R>(merge, s, a, st); break;
+    case 1: e = launch_v<BF16, R>(merge, s, a, st); break;
+    case 2: e = launch_v<F16, R>(merge, s, a, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    if (ev_after) {
+        e = hipEventRecord(ev_after, st);
+        if (e != hipSuccess) return e;
+    }
+    if (merge && a.n > 0) {
+        hipLaunchKernelGGL((k_merge_fixup<R>), dim3((uint32_t)a.P), dim3(kWave), 0, st, a.C, a.ld,
+                           (int)a.n, a.carry_vals, a.carry_rows, a.P);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 }  // namespace spmmk

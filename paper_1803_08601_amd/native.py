@@ -19,6 +19,7 @@ SPMM_OK, SPMM_ERR_INVALID, SPMM_ERR_UNSUPPORTED, SPMM_ERR_HIP, SPMM_ERR_NOMEM, S
 SPMM_F32, SPMM_BF16, SPMM_F16 = 0, 1, 2
 SPMM_MODE_PAPER, SPMM_MODE_AUTOTUNE, SPMM_MODE_ROWSPLIT, SPMM_MODE_MERGE = 0, 1, 2, 3
 SPMM_KERNEL_ROWSPLIT, SPMM_KERNEL_MERGE = 0, 1
+SPMM_PLUS_TIMES, SPMM_MIN_PLUS, SPMM_MAX_PLUS, SPMM_MAX_TIMES = 0, 1, 2, 3
 
 MODES = {"paper": SPMM_MODE_PAPER, "autotune": SPMM_MODE_AUTOTUNE,
          "rowsplit": SPMM_MODE_ROWSPLIT, "merge": SPMM_MODE_MERGE}
@@ -65,6 +66,7 @@ _SIGS = {
     "spmm_plan_create_config": [_VP, _VP, _VP, _I64, _I64, _I64, _I64, _I64, _I32, _VP, _VP],
     "spmm_execute": [_VP, _VP, _VP, _VP, _VP],
     "spmm_execute_events": [_VP, _VP, _VP, _VP, _VP, _VP, _VP],
+    "spmm_execute_semiring": [_VP, _I32, _VP, _VP, _VP, _VP],
     "spmm_plan_info_get": [_VP, _VP],
     "spmm_plan_partition": [_VP, _VP, _I64],
     "spmm_plan_destroy": [_VP],
@@ -180,6 +182,11 @@ def spmm_execute_events(plan, A_vals, B, C, ev_before, ev_after, stream=None):
         plan, _ptr(A_vals), _ptr(B), _ptr(C), ev_before, ev_after, _stream(stream)))
 
 
+def spmm_execute_semiring(plan, semiring, A_vals, B, C, stream=None):
+    return _check("spmm_execute_semiring", lib().spmm_execute_semiring(
+        plan, semiring, _ptr(A_vals), _ptr(B), _ptr(C), _stream(stream)))
+
+
 def spmm_plan_info_get(plan):
     info = spmm_plan_info()
     _check("spmm_plan_info_get", lib().spmm_plan_info_get(plan, ctypes.byref(info)))
@@ -273,6 +280,10 @@ class Plan:
 
     def execute(self, vals, B, C, stream=None):
         spmm_execute(self.handle, vals, B, C, stream)
+        return C
+
+    def execute_semiring(self, semiring, vals, B, C, stream=None):
+        spmm_execute_semiring(self.handle, semiring, vals, B, C, stream)
         return C
 
     def partition(self):

@@ -342,3 +342,52 @@ def test_merge_closed_forms():
 ])
 def test_heuristic_table(m, nnz, merge):
     assert oracle.heuristic_merge(m, nnz) == merge
+
+
+# ---------------------------------------------------------------- semirings
+
+def _dense_with(A, fill):
+    D = np.full((A.m, A.k), fill, dtype=np.float64)
+    rows = np.repeat(np.arange(A.m), A.row_lengths())
+    D[rows, A.colind] = A.vals
+    return D
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_semirings_brute_force(seed):
+    """Brute force over every (i, j, c) with numpy broadcasting; missing
+    entries take the value that never wins (+inf for min, -inf for max)."""
+    rng = np.random.default_rng(seed)
+    A = wl.random_csr(seed, 30, 25, density=0.2, empty_frac=0.2, dtype=np.float64)
+    B = rng.uniform(-2, 2, (25, 6))
+    C = oracle.spmm_semiring(A.rowptr, A.colind, A.vals, B, oracle.PLUS_TIMES)
+    assert np.allclose(C, dense_of(A) @ B, rtol=1e-13, atol=1e-13)
+    C = oracle.spmm_semiring(A.rowptr, A.colind, A.vals, B, oracle.MIN_PLUS)
+    assert np.array_equal(C, np.min(_dense_with(A, np.inf)[:, :, None] + B[None], axis=1))
+    C = oracle.spmm_semiring(A.rowptr, A.colind, A.vals, B, oracle.MAX_PLUS)
+    assert np.array_equal(C, np.max(_dense_with(A, -np.inf)[:, :, None] + B[None], axis=1))
+    D = _dense_with(A, np.nan)
+    prod = np.where(np.isnan(D)[:, :, None], -np.inf, np.nan_to_num(D)[:, :, None] * B[None])
+    C = oracle.spmm_semiring(A.rowptr, A.colind, A.vals, B, oracle.MAX_TIMES)
+    assert np.array_equal(C, np.max(prod, axis=1))
+
+
+def test_min_plus_bellman_ford_matches_scipy_shortest_paths():
+    """Repeated min-plus products relax distances (Bellman-Ford); after |V|
+    rounds they equal scipy's shortest-path distances."""
+    from scipy.sparse.csgraph import shortest_path
+    rng = np.random.default_rng(3)
+    N = 40
+    A = wl.random_csr(3, N, N, density=0.1)
+    A.vals = rng.integers(1, 10, A.nnz).astype(np.float64)
+    # A^T as CSR: row v lists its in-edges (u, w), so d'[v] = min_u w(u,v) + d[u]
+    at_rp, at_ci, perm = oracle.transpose(A.rowptr, A.colind, N)
+    at_v = A.vals[perm]
+    src = [0, 5, 17]
+    d = np.full((N, len(src)), np.inf)
+    d[src, np.arange(len(src))] = 0.0
+    for _ in range(N):
+        relax = oracle.spmm_semiring(at_rp, at_ci, at_v, d, oracle.MIN_PLUS)
+        d = np.minimum(d, relax)
+    ref = shortest_path(scipy_of(A), method="BF", directed=True, indices=src).T
+    assert np.array_equal(d, ref)

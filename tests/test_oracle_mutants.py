@@ -14,7 +14,11 @@ SRC = os.path.join(ROOT, "oracle", "spmm_oracle.c")
 MUTANTS = {
     "drop_last_term": ("p < rowptr[i + 1]; ++p) {\n        double a = or_load(vals, p, vdt);\n        int64_t r",
                        "p + 1 < rowptr[i + 1]; ++p) {\n        double a = or_load(vals, p, vdt);\n        int64_t r"),
-    "wrong_sign": ("out[c] += a * b;", "out[c] -= a * b;"),
+    "wrong_sign": ("if (absval) b = fabs(b);\n            out[c] += a * b;",
+                   "if (absval) b = fabs(b);\n            out[c] -= a * b;"),
+    "semiring_min_as_max": ("case 1: out[c] = fmin(out[c], a + b);", "case 1: out[c] = fmax(out[c], a + b);"),
+    "semiring_identity": ("semiring == 1 ? INFINITY : -INFINITY", "semiring == 1 ? -INFINITY : -INFINITY"),
+    "semiring_times_as_plus": ("default: out[c] = fmax(out[c], a * b);", "default: out[c] = fmax(out[c], a + b);"),
     "transposed_B": ("double b = or_load(B, r * ldb + c, bdt);\n            if (absval) b = fabs(b);\n            out[c]",
                      "double b = or_load(B, c * ldb + r, bdt);\n            if (absval) b = fabs(b);\n            out[c]"),
     "abs_dropped": ("if (absval) b = fabs(b);\n            out[c]", "out[c]"),
@@ -32,7 +36,8 @@ MUTANTS = {
 BATTERY = ["test_worked_example", "test_spmm_matches_dense_gemm", "test_identity_permutation",
            "test_row_sum", "test_transpose_vs_scipy", "test_merge_walk_invariants",
            "test_merge_closed_forms", "test_heuristic_table", "test_bf16_and_f16_decoders",
-           "test_gradients_euler", "test_spmm_t_and_sddmm_vs_dense"]
+           "test_gradients_euler", "test_spmm_t_and_sddmm_vs_dense", "test_semirings_brute_force",
+           "test_min_plus_bellman"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
