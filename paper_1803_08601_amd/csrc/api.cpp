@@ -188,11 +188,11 @@ static int check_config(const spmm_plan_s& p, spmm_config& c) {
 struct TuneKey {
     int device;
     int64_t m, k, nnz, n, ld, maxrow, longrows;
-    int dtype, unroll;
+    int dtype, unroll, max_W;
     bool operator<(const TuneKey& o) const {
-        return std::tie(device, m, k, nnz, n, ld, maxrow, longrows, dtype, unroll) <
+        return std::tie(device, m, k, nnz, n, ld, maxrow, longrows, dtype, unroll, max_W) <
                std::tie(o.device, o.m, o.k, o.nnz, o.n, o.ld, o.maxrow, o.longrows, o.dtype,
-                        o.unroll);
+                        o.unroll, o.max_W);
     }
 };
 static std::map<TuneKey, std::pair<spmm_config, double>> g_tuned;
@@ -222,7 +222,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     const int max_W = opts ? opts->max_W : 0;
     const bool own = opts && opts->C && (p.nnz == 0 || (opts->vals && opts->B));
     const TuneKey key{p.device, p.m, p.k, p.nnz, p.n, p.ld, p.max_row_len, p.long_rows, p.dtype,
-                      fixed_unroll * 65536 + max_W};
+                      fixed_unroll, max_W};
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tuned.find(key);
