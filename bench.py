@@ -273,6 +273,7 @@ def heuristic_sweep(n=64):
             rp = torch.arange(0, (m + 1) * L, L, dtype=torch.int64, device="cuda").to(torch.int32)
             ci = torch.arange(L, dtype=torch.int32, device="cuda").repeat(m)
             k, nnz, desc = L, m * L, f"dense {m} x {L}"
+            maxrow = L
         else:
             shape, mean = a, b
             rng = np.random.default_rng(int(shape * 100 + mean))
@@ -281,6 +282,7 @@ def heuristic_sweep(n=64):
             rp = torch.from_numpy(wl.rowptr_from_lengths(lengths)).cuda()
             ci = torch.from_numpy(cols).cuda()
             m, k, nnz = 1_000_000, 1_000_000, int(lengths.sum())
+            maxrow = int(lengths.max())
             desc = f"power law, tail exponent {shape + 1.0:.1f}, mean {mean:g}, 1M x 1M"
         g = torch.Generator(device="cuda")
         g.manual_seed(7)
@@ -290,11 +292,12 @@ def heuristic_sweep(n=64):
         rs = _best_of(nv, rp, ci, m, k, nnz, n, vals, Bt, C, "rowsplit")
         mg = _best_of(nv, rp, ci, m, k, nnz, n, vals, Bt, C, "merge")
         d = nnz / m
-        rec = {"matrix": desc, "m": m, "k": k, "nnz": nnz, "mean_row": d,
+        rec = {"matrix": desc, "m": m, "k": k, "nnz": nnz, "mean_row": d, "max_row": maxrow,
                "rowsplit_ms": round(rs[0], 4), "merge_ms": round(mg[0], 4),
                "rowsplit_shape": rs[1], "merge_shape": mg[1],
                "faster": "merge" if mg[0] < rs[0] else "rowsplit",
-               "paper_rule": "merge" if 100 * nnz < 935 * m else "rowsplit"}
+               "paper_rule": "merge" if 100 * nnz < 935 * m else "rowsplit",
+               "mi355x_rule": "merge" if (nnz < 4 * m or maxrow >= 4096) else "rowsplit"}
         print(json.dumps(rec), flush=True)
         recs.append(rec)
         del rp, ci, vals, Bt, C
@@ -312,7 +315,15 @@ def heuristic_sweep(n=64):
             pick = r["merge_ms"] if r["mean_row"] < th else r["rowsplit_ms"]
             tot += np.log(pick / min(r["merge_ms"], r["rowsplit_ms"]))
         return float(np.exp(tot / len(recs)))
+    def rule_stats(key):
+        ok = [r[key] == r["faster"] for r in recs]
+        tot = sum(np.log((r["merge_ms"] if r[key] == "merge" else r["rowsplit_ms"])
+                         / min(r["merge_ms"], r["rowsplit_ms"])) for r in recs)
+        return round(sum(ok) / len(ok), 3), round(float(np.exp(tot / len(recs))), 3)
+    mi_acc, mi_loss = rule_stats("mi355x_rule")
     print(json.dumps({"summary": "heuristic sweep", "n": n, "matrices": len(recs),
+                      "mi355x_rule": "merge if mean < 4 or longest row >= 4096",
+                      "mi355x_rule_accuracy": mi_acc, "mi355x_rule_geomean_slowdown": mi_loss,
                       "paper_threshold": 9.35, "paper_rule_accuracy": round(acc(9.35), 3),
                       "paper_rule_geomean_slowdown": round(loss(9.35), 3),
                       "best_threshold": best_th, "best_threshold_accuracy": round(acc(best_th), 3),

@@ -65,12 +65,18 @@ typedef enum spmm_dtype { SPMM_F32 = 0, SPMM_BF16 = 1, SPMM_F16 = 2 } spmm_dtype
  *              100 * nnz < 935 * m).
  *   AUTOTUNE : time the candidate kernels and shapes on scratch buffers of
  *              the plan's sizes and keep the fastest.
- *   ROWSPLIT / MERGE : force that kernel with default shapes. */
+ *   ROWSPLIT / MERGE : force that kernel with default shapes.
+ *   RULE     : the O(1) rule re-derived on MI355X from the kernel-choice
+ *              sweep (the Sec. 5.4 procedure on this GPU): merge-based when
+ *              the mean row length is below 4 or the longest row has 4096
+ *              or more entries (row split cannot spread one row over
+ *              several workgroups), row split otherwise. */
 typedef enum spmm_mode {
     SPMM_MODE_PAPER = 0,
     SPMM_MODE_AUTOTUNE = 1,
     SPMM_MODE_ROWSPLIT = 2,
-    SPMM_MODE_MERGE = 3
+    SPMM_MODE_MERGE = 3,
+    SPMM_MODE_RULE = 4
 } spmm_mode;
 
 typedef enum spmm_kernel { SPMM_KERNEL_ROWSPLIT = 0, SPMM_KERNEL_MERGE = 1 } spmm_kernel;

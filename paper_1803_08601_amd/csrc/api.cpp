@@ -351,6 +351,16 @@ static int row_stats(spmm_plan_s& p, hipStream_t st) {
     return SPMM_OK;
 }
 
+// Kernel choice re-derived on MI355X (mode RULE): merge-based for very short
+// rows on average (mean below 4) and whenever one row is long enough that a
+// single row-split team would hold up the grid (4096 entries or more).
+static int rule_choice(const spmm_plan_s& p) {
+    if (p.m == 0) return SPMM_KERNEL_ROWSPLIT;
+    const bool short_rows = p.nnz < 4 * p.m;
+    const bool long_row = p.max_row_len >= 4096;
+    return short_rows || long_row ? SPMM_KERNEL_MERGE : SPMM_KERNEL_ROWSPLIT;
+}
+
 static int check_dims(int64_t m, int64_t k, int64_t nnz, int64_t n, int64_t ld) {
     const int64_t lim = (int64_t(1) << 31) - 1;
     if (m < 0 || k < 0 || nnz < 0 || n < 0)
@@ -388,7 +398,7 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
     if (rc) return rc;
     if (dtype != SPMM_F32 && dtype != SPMM_BF16 && dtype != SPMM_F16)
         return fail(SPMM_ERR_UNSUPPORTED, "dtype %d", dtype);
-    if (!forced && (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_MERGE))
+    if (!forced && (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_RULE))
         return fail(SPMM_ERR_INVALID, "mode %d", mode);
     if (m > 0 && !rowptr) return fail(SPMM_ERR_INVALID, "A_rowptr is NULL");
     if (nnz > 0 && !colind) return fail(SPMM_ERR_INVALID, "A_colind is NULL");
@@ -414,6 +424,7 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
             rc = autotune(*p, st, opts);
         } else {
             const int kern = mode == SPMM_MODE_PAPER    ? p->paper_choice
+                             : mode == SPMM_MODE_RULE  ? rule_choice(*p)
                              : mode == SPMM_MODE_MERGE ? SPMM_KERNEL_MERGE
                                                         : SPMM_KERNEL_ROWSPLIT;
             p->cfg = spmm_config{kern, 0, 0, opts ? opts->fixed_unroll : 0, 0};

@@ -85,7 +85,7 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
     if (count > 0 && !problems_host) return fail(SPMM_ERR_INVALID, "problems is NULL");
     if (dtype != SPMM_F32 && dtype != SPMM_BF16 && dtype != SPMM_F16)
         return fail(SPMM_ERR_UNSUPPORTED, "dtype %d", dtype);
-    if (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_MERGE) return fail(SPMM_ERR_INVALID, "mode %d", mode);
+    if (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_RULE) return fail(SPMM_ERR_INVALID, "mode %d", mode);
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     spmm_batch_s* b = new (std::nothrow) spmm_batch_s;

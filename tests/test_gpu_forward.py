@@ -229,3 +229,17 @@ def test_validate():
     bad[50] = bad[51] + 1
     with pytest.raises(nv.SpmmError):
         nv.spmm_csr_validate(dev(bad), ci, A.m, A.k, A.nnz)
+
+
+def test_rule_mode_choice():
+    """The MI355X rule: merge-based for power-law rows (a row of >= 4096
+    entries) or a mean below 4, row split for regular rows."""
+    cases = [(wl.power_law(seed=51, m=40_000, cap=20_000), nv.SPMM_KERNEL_MERGE),
+             (wl.stencil27(g=20), nv.SPMM_KERNEL_ROWSPLIT),
+             (wl.plain(m=2000, k=2000), nv.SPMM_KERNEL_ROWSPLIT),
+             (wl.random_csr(8, 5000, 4000, density=0.0005), nv.SPMM_KERNEL_MERGE)]
+    for A, want in cases:
+        B = wl.dense(5, A.k, 16)
+        C, plan = run(A, dev(A.vals), dev(B), 16, mode="rule")
+        assert plan.info().config.kernel == want
+        check(A, dev(A.vals), dev(B), 16, C)
