@@ -125,12 +125,6 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
         float nv0 = 0.f, nv1 = 0.f;
         if (more) load_pair(base + CH, nc0, nv0, nc1, nv1);
         const int nsteps = (cnt + (1 << ts_log2) - 1) >> ts_log2;
-        // Software pipeline: the gathers of step group s are issued before the
-        // products of group s - U are accumulated, so two groups of B rows are
-        // in flight while the slot waits.
-        float pb[U][VEC], pv[U];
-        bool pok[U];
-        bool pending = false;
         for (int s = 0; s < nsteps; s += U) {
             int c[U];
             float v[U];
@@ -157,30 +151,11 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
                     for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
                 }
             }
-            if (pending) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (R::kZeroTermIsNeutral || pok[u]) {
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], pv[u], pb[u][e]);
-                    }
-                }
-            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                pv[u] = v[u];
-                pok[u] = ok[u];
+                if (R::kZeroTermIsNeutral || ok[u]) {
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) pb[u][e] = b[u][e];
-            }
-            pending = true;
-        }
-        if (pending) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (R::kZeroTermIsNeutral || pok[u]) {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], pv[u], pb[u][e]);
+                    for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
                 }
             }
         }
