@@ -401,6 +401,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true",
                     help="only the headline product (skip the GCN fwd+bwd and batched extras)")
+    ap.add_argument("--only-extra", choices=["gcn", "batch"],
+                    help="run just one extra measurement and print its JSON (for profiling)")
     ap.add_argument("--sweep", action="store_true",
                     help="kernel-choice sweep over mean row length (re-derives the Sec. 5.4 threshold)")
     ap.add_argument("--crossover", action="store_true",
@@ -420,6 +422,10 @@ def main():
 
     if args.sweep:
         heuristic_sweep(args.n)
+        return
+    if args.only_extra:
+        rec = gcn_fwd_bwd(args.steps, args.warmup) if args.only_extra == "gcn" else batched(args.steps, args.warmup)
+        print(json.dumps(rec), flush=True)
         return
     if args.crossover:
         crossover(args.n)

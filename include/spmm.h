@@ -99,6 +99,10 @@ typedef struct spmm_config {
     int32_t unroll;        /* B-row gathers in flight per lane group: 1, 2, 4 or 8 */
     int32_t items_per_wg;  /* merge-based (Sec. 4.2): merge items (rows + nonzeros) per
                               workgroup, 64 .. 8192 */
+    int32_t tile_cols;     /* columns per column tile (Fig. 3(a)'s 2-D grid): a multiple of
+                              vec; the product runs over ceil(n / tile_cols) tiles, each
+                              re-reading A but touching only its columns of B. 0 = as wide as
+                              one wavefront covers (64 * vec columns) */
 } spmm_config;
 
 typedef struct spmm_plan_info {

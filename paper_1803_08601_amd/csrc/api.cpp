@@ -52,10 +52,11 @@ static int ilog2_ceil(int64_t x) {
     return l;
 }
 
-// Lanes that cover one B row (capped at a wavefront; wider rows use column
-// tiles) and the resulting number of column tiles.
-void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles) {
-    int64_t lanes = (n + vec - 1) / vec;
+// Lanes that cover one column tile of a B row (the whole row up to a
+// wavefront, or tile_cols columns when given) and the number of column tiles.
+void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles, int tile_cols) {
+    const int64_t width = tile_cols > 0 && tile_cols < n ? tile_cols : n;
+    int64_t lanes = (width + vec - 1) / vec;
     if (lanes < 1) lanes = 1;
     if (lanes > spmmk::kWaveSize) lanes = spmmk::kWaveSize;
     *g_log2 = ilog2_ceil(lanes);
@@ -67,7 +68,7 @@ void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles) {
 spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec) {
     spmmk::Shape s;
     s.vec = vec;
-    slot_geometry(p.n, vec, &s.g_log2, &s.col_tiles);
+    slot_geometry(p.n, vec, &s.g_log2, &s.col_tiles, p.cfg.tile_cols);
     int lpr = std::max<int>(p.cfg.lanes_per_row, 1 << s.g_log2);
     lpr = std::min(lpr, spmmk::kWaveSize);
     s.ts_log2 = ilog2_ceil(lpr) - s.g_log2;
@@ -146,8 +147,11 @@ static int check_config(const spmm_plan_s& p, spmm_config& c) {
         return fail(SPMM_ERR_UNSUPPORTED, "config.vec %d: use 1 or %d for this dtype", c.vec, v16);
     if (c.vec == v16 && !can16)
         return fail(SPMM_ERR_UNSUPPORTED, "config.vec %d needs n and ld divisible by %d", c.vec, v16);
+    if (c.tile_cols < 0 || (c.tile_cols % c.vec) != 0)
+        return fail(SPMM_ERR_UNSUPPORTED, "config.tile_cols %d: a multiple of vec %d", c.tile_cols,
+                    c.vec);
     int g_log2, tiles;
-    slot_geometry(p.n, c.vec, &g_log2, &tiles);
+    slot_geometry(p.n, c.vec, &g_log2, &tiles, c.tile_cols);
     const int g = 1 << g_log2;
     if (c.unroll == 0) c.unroll = 4;
     if (c.unroll != 1 && c.unroll != 2 && c.unroll != 4 && c.unroll != 8)
@@ -202,18 +206,29 @@ static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_
     std::vector<spmm_config> out;
     const int v16 = vec16(p.dtype);
     const int vec = (p.n % v16 == 0 && p.ld % v16 == 0) ? v16 : 1;
-    int g_log2, tiles;
-    slot_geometry(p.n, vec, &g_log2, &tiles);
     std::vector<int> unrolls = {2, 4, 8};
     if (fixed_unroll) unrolls = {fixed_unroll};
+    // Column tiles: the full row width, and for wide rows half of it (each
+    // tile re-reads A but gathers only its half of every B row, which halves
+    // the set of B lines a workgroup keeps in cache).
+    std::vector<int> tiles = {0};
+    if (p.n >= 64 && p.n % (2 * vec) == 0) tiles.push_back((int)(p.n / 2));
     // Merge-based first: its time does not depend on row lengths, so it sets
     // a bar that lets hopeless row-split shapes stop after one run. Row split
     // goes from whole-wavefront teams (best for long rows) down.
-    for (int W : {2048, 1024, 4096, 512})
-        if (!max_W || W <= max_W)
-            for (int u : unrolls) out.push_back({SPMM_KERNEL_MERGE, vec, 1 << g_log2, u, W});
-    for (int lpr = spmmk::kWaveSize; lpr >= (1 << g_log2); lpr /= 2)
-        for (int u : unrolls) out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024});
+    for (int tc : tiles) {
+        int g_log2, nt;
+        slot_geometry(p.n, vec, &g_log2, &nt, tc);
+        for (int W : {2048, 1024, 4096, 512})
+            if (!max_W || W <= max_W)
+                for (int u : unrolls) out.push_back({SPMM_KERNEL_MERGE, vec, 1 << g_log2, u, W, tc});
+    }
+    for (int tc : tiles) {
+        int g_log2, nt;
+        slot_geometry(p.n, vec, &g_log2, &nt, tc);
+        for (int lpr = spmmk::kWaveSize; lpr >= (1 << g_log2); lpr /= 2)
+            for (int u : unrolls) out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024, tc});
+    }
     return out;
 }
 
@@ -233,7 +248,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
         }
     }
     if (p.m == 0 || p.n == 0) {
-        p.cfg = spmm_config{p.paper_choice, 0, 0, fixed_unroll, 0};
+        p.cfg = spmm_config{p.paper_choice, 0, 0, fixed_unroll, 0, 0};
         return check_config(p, p.cfg);
     }
     const int eb = elem_bytes(p.dtype);
@@ -427,7 +442,7 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
                              : mode == SPMM_MODE_RULE  ? rule_choice(*p)
                              : mode == SPMM_MODE_MERGE ? SPMM_KERNEL_MERGE
                                                         : SPMM_KERNEL_ROWSPLIT;
-            p->cfg = spmm_config{kern, 0, 0, opts ? opts->fixed_unroll : 0, 0};
+            p->cfg = spmm_config{kern, 0, 0, opts ? opts->fixed_unroll : 0, 0, 0};
             rc = check_config(*p, p->cfg);
         }
     }

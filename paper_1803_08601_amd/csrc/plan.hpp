@@ -63,7 +63,7 @@ constexpr int kSddmmW = 2048;
 
 bool plan_alive(const spmm_plan_s* p);
 bool aligned16(const void* ptr);
-void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles);
+void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles, int tile_cols = 0);
 int elem_bytes(int dtype);
 int vec16(int dtype);
 spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec);

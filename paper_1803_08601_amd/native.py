@@ -28,7 +28,7 @@ MODES = {"paper": SPMM_MODE_PAPER, "autotune": SPMM_MODE_AUTOTUNE,
 class spmm_config(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("vec", ctypes.c_int32),
                 ("lanes_per_row", ctypes.c_int32), ("unroll", ctypes.c_int32),
-                ("items_per_wg", ctypes.c_int32)]
+                ("items_per_wg", ctypes.c_int32), ("tile_cols", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -75,5 +75,5 @@ def test_spmm_csr_noop_and_checks():
 
 
 def test_config_struct_layout():
-    assert ctypes.sizeof(nv.spmm_config) == 20
+    assert ctypes.sizeof(nv.spmm_config) == 24
     assert ctypes.sizeof(nv.spmm_problem) == 5 * 8 + 5 * 8

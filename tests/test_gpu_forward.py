@@ -46,11 +46,14 @@ CONFIGS = [
     dict(kernel=MG, items_per_wg=256, unroll=2),
     dict(kernel=MG, items_per_wg=1024, unroll=4),
     dict(kernel=MG, items_per_wg=4096, unroll=8),
+    dict(kernel=RS, lanes_per_row=16, unroll=4, tile_cols=32),
+    dict(kernel=MG, items_per_wg=512, unroll=4, tile_cols=32),
 ]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"{'rs' if c['kernel'] == 0 else 'mg'}-"
-                         f"{c.get('lanes_per_row', c.get('items_per_wg'))}-u{c['unroll']}")
+                         f"{c.get('lanes_per_row', c.get('items_per_wg'))}-u{c['unroll']}"
+                         f"-t{c.get('tile_cols', 0)}")
 @pytest.mark.parametrize("n", [1, 8, 32, 64, 100, 128, 512])
 def test_plain_configs(cfg, n):
     A = wl.plain(m=1000, k=900)
@@ -83,7 +86,8 @@ def test_stencil_modes(mode):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 @pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"{'rs' if c['kernel'] == 0 else 'mg'}-"
-                         f"{c.get('lanes_per_row', c.get('items_per_wg'))}-u{c['unroll']}")
+                         f"{c.get('lanes_per_row', c.get('items_per_wg'))}-u{c['unroll']}"
+                         f"-t{c.get('tile_cols', 0)}")
 def test_integer_exact(dtype, cfg):
     """Integer values: every partial sum is exact, so any summation order must
     reproduce the oracle bit for bit (catches dropped or doubled partials)."""
