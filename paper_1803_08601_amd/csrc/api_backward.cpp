@@ -8,15 +8,9 @@ using namespace spmmh;
 
 namespace {
 
-// Entries in flight per SDDMM slot, by vector width (16-bit rows carry 8-wide
-// chunks of B and dC, so fewer fit in registers at full occupancy).
-#ifndef SPMM_SDDMM_UNROLL_WIDE
-#define SPMM_SDDMM_UNROLL_WIDE 2
-#endif
-#ifndef SPMM_SDDMM_UNROLL
-#define SPMM_SDDMM_UNROLL 4
-#endif
-int sddmm_unroll(int vec) { return vec == 8 ? SPMM_SDDMM_UNROLL_WIDE : SPMM_SDDMM_UNROLL; }
+// SDDMM keeps 4 entries in flight per slot, 2 with 8-wide 16-bit rows (whose
+// dC chunks take 8 registers each) so that occupancy stays at 8 waves/SIMD.
+int sddmm_unroll(int vec) { return vec == 8 ? 2 : 4; }
 
 }  // namespace
 

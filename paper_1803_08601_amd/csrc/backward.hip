@@ -218,9 +218,8 @@ hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int
 // in LDS; its slots (2^g_log2 lanes covering one column tile of a row) split
 // the piece evenly with the diagonal search on the LDS copy and walk their
 // entries in order, finding each entry's row among the staged row ends. For U
-// entries at a time a slot gathers the B row chunks and, for entries that
-// start a new row, the dC row chunk (other entries reuse the chunk in
-// registers), forms
+// entries at a time a slot gathers the B row chunks and the dC row chunks
+// (the latter mostly cache hits, as neighbouring entries share rows), forms
 // the partial dot products over all column tiles, and sums its lanes with DPP
 // row exchanges; lane 0 writes dvals. No entry depends on another, so there is
 // no carry-out.
@@ -263,13 +262,6 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr
     const int js = d0 - r;
     const int je = d1 - search(d1);
     const int span = VEC << g_log2;
-    // With one column tile the dC chunk of the current row stays in registers
-    // and is reloaded only when the walk reaches a new row.
-    const bool keep = col_tiles == 1;
-    int prev_row = -1;
-    float dprev[VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) dprev[e] = 0.f;
     for (int jb = js; jb < je; jb += U) {
         int rr[U], c[U];
         float part[U];
@@ -285,36 +277,24 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr
             rr[u] = r;
             part[u] = 0.f;
         }
-        bool fresh[U];  // entry u needs its own dC chunk
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            fresh[u] = !keep || (u == 0 ? rr[0] != prev_row : rr[u] != rr[u - 1]);
         for (int t = 0; t < col_tiles; ++t) {
             const int col = t * span + g * VEC;
             const bool col_ok = col < n;
             float b[U][VEC], d[U][VEC];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) b[u][e] = d[u][e] = 0.f;
                 if (jb + u < je && col_ok) {
                     load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
-                    if (fresh[u]) load_f32<VEC>(dC + (int64_t)(i0 + rr[u]) * ld + col, d[u]);
+                    load_f32<VEC>(dC + (int64_t)(i0 + rr[u]) * ld + col, d[u]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) b[u][e] = d[u][e] = 0.f;
                 }
             }
-            float dcur[VEC];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    dcur[e] = fresh[u] ? d[u][e] : (u == 0 ? dprev[e] : dcur[e]);
-                    part[u] = fmaf(dcur[e], b[u][e], part[u]);
-                }
-            }
-            if (keep) {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) dprev[e] = dcur[e];
-                prev_row = rr[U - 1];
+                for (int e = 0; e < VEC; ++e) part[u] = fmaf(d[u][e], b[u][e], part[u]);
             }
         }
 #pragma unroll
