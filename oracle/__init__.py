@@ -49,6 +49,9 @@ def lib():
         L.oracle_merge_num_parts.argtypes = [i64, i64, i64]
         L.oracle_merge_num_parts.restype = i64
         L.oracle_merge_partition.argtypes = [i64, i32p, i64, i32p]
+        L.oracle_nz_num_parts.argtypes = [i64, i64, i64]
+        L.oracle_nz_num_parts.restype = i64
+        L.oracle_nz_partition.argtypes = [i64, i32p, i64, i32p]
         L.oracle_heuristic_merge.argtypes = [i64, i64]
         L.oracle_decode.argtypes = [vp, i64, ctypes.c_int]
         L.oracle_decode.restype = ctypes.c_double
@@ -205,6 +208,22 @@ def merge_partition(rowptr, W):
     P = merge_num_parts(m, int(rowptr[m]), W)
     out = np.empty((P + 1, 2), dtype=np.int32)
     assert lib().oracle_merge_partition(m, _p(rowptr), W, _p(out)) == 0
+    return out
+
+
+def nz_num_parts(m, nnz, W):
+    return int(lib().oracle_nz_num_parts(m, nnz, W))
+
+
+def nz_partition(rowptr, W):
+    """Nonzero split (Sec. 4): piece p starts at nonzero min(p*W, nnz) in the
+    row found by a 1-D search on the row offsets; shape (P+1, 2) of (row,
+    nonzero) merge states, first (0, 0), last (m, nnz)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    m = rowptr.shape[0] - 1
+    P = nz_num_parts(m, int(rowptr[m]), W)
+    out = np.empty((P + 1, 2), dtype=np.int32)
+    assert lib().oracle_nz_partition(m, _p(rowptr), W, _p(out)) == 0
     return out
 
 

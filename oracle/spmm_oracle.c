@@ -18,6 +18,8 @@
  *   - the merge-path coordinates of Sec. 4 (2-D search on the diagonals of
  *     the merge of row offsets with nonzero indices), both by a sequential
  *     walk of the merge and by binary search;
+ *   - the nonzero split of Sec. 4 (equal nonzeros per piece, start row by
+ *     a 1-D binary search on the row offsets);
  *   - the paper's mean-row-length heuristic of Sec. 5.4.
  *
  * Inputs arrive in their storage type (fp64, fp32, bf16 or fp16 bit
@@ -306,6 +308,52 @@ int oracle_merge_partition(int64_t m, const int32_t* rowptr, int64_t W, int32_t*
         int64_t i, j;
         oracle_merge_search(m, rowptr, d, &i, &j);
         coords[2 * p] = (int32_t)i;
+        coords[2 * p + 1] = (int32_t)j;
+    }
+    return 0;
+}
+
+/* ---- nonzero split (Sec. 4, item (a) of the load-balancing schemes) ----
+ *
+ * Every piece gets the same number W of nonzeros: piece p starts at
+ * nonzero j_p = min(p * W, nnz), and a 1-D binary search on the row offsets
+ * finds the row it starts in, i.e. the row holding nonzero j_p. Expressed as
+ * a state of the merge above, piece p starts at (i_p, j_p) with i_p the
+ * number of rows whose end rowptr[i+1] is <= j_p (those rows, empty ones
+ * included, are finished before nonzero j_p is taken). The first piece
+ * starts at (0, 0) so that it also finishes the leading empty rows, and the
+ * last piece ends at (m, nnz). P = ceil(nnz / W), at least 1 when m > 0
+ * (a matrix without nonzeros is one piece of empty rows); P = 0 when m = 0.
+ */
+int64_t oracle_nz_num_parts(int64_t m, int64_t nnz, int64_t W) {
+    if (W <= 0) return -1;
+    if (m == 0) return 0;
+    int64_t P = (nnz + W - 1) / W;
+    return P > 0 ? P : 1;
+}
+
+/* Number of rows whose end is <= j: the 1-D binary search on row offsets. */
+static int64_t or_rows_ended_by(int64_t m, const int32_t* rowptr, int64_t j) {
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if ((int64_t)rowptr[mid + 1] <= j)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+int oracle_nz_partition(int64_t m, const int32_t* rowptr, int64_t W, int32_t* coords) {
+    if (m < 0 || W <= 0) return -1;
+    int64_t nnz = rowptr[m];
+    int64_t P = oracle_nz_num_parts(m, nnz, W);
+    coords[0] = 0;
+    coords[1] = 0;
+    for (int64_t p = 1; p <= P; ++p) {
+        int64_t j = p * W < nnz ? p * W : nnz;
+        coords[2 * p] = (int32_t)(p == P ? m : or_rows_ended_by(m, rowptr, j));
         coords[2 * p + 1] = (int32_t)j;
     }
     return 0;

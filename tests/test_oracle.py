@@ -328,6 +328,57 @@ def test_merge_closed_forms():
     assert np.array_equal(w[:, 0], d // 2) and np.array_equal(w[:, 1], d - d // 2)
 
 
+# ---------------------------------------------------------------- nonzero split
+
+@pytest.mark.parametrize("name,rowptr", list(_adversarial().items()))
+def test_nz_partition_against_merge_walk(name, rowptr):
+    """Piece p of the nonzero split starts at the last merge state whose
+    nonzero coordinate is min(p*W, nnz): the state from which nonzero p*W is
+    the next item (all row ends up to it, empty rows included, are taken
+    first). The merge walk is pinned on its own above."""
+    m = rowptr.shape[0] - 1
+    nnz = int(rowptr[-1])
+    walk = oracle.merge_walk(rowptr)
+    last_at_j = {}
+    for i, j in walk:
+        last_at_j[int(j)] = int(i)
+    for W in (1, 2, 3, 7, 64, 1000):
+        part = oracle.nz_partition(rowptr, W)
+        P = oracle.nz_num_parts(m, nnz, W)
+        assert part.shape[0] == P + 1
+        if m == 0:
+            assert P == 0 and tuple(part[0]) == (0, 0)
+            continue
+        assert P == max(1, -(-nnz // W))
+        assert tuple(part[0]) == (0, 0) and tuple(part[-1]) == (m, nnz)
+        # equal nonzeros per piece, the last one takes the rest
+        assert np.array_equal(part[:, 1], np.minimum(np.arange(P + 1) * W, nnz))
+        for p in range(1, P):
+            i, j = part[p]
+            assert i == last_at_j[int(j)]
+            # row i holds nonzero j (the 1-D search on the row offsets)
+            assert rowptr[i] <= j < rowptr[i + 1]
+        assert np.all(np.diff(part[:, 0]) >= 0)
+
+
+def test_nz_partition_closed_forms():
+    # constant row length L, no empty rows: piece p starts in row p*W // L
+    for m, L, W in ((100, 3, 7), (64, 16, 64), (10, 1, 4), (33, 5, 5)):
+        rp = np.arange(0, (m + 1) * L, L, dtype=np.int32)
+        part = oracle.nz_partition(rp, W)
+        P = part.shape[0] - 1
+        assert P == -(-(m * L) // W)
+        for p in range(P):
+            assert tuple(part[p]) == ((p * W) // L, p * W)
+        assert tuple(part[P]) == (m, m * L)
+    # no nonzeros: one piece of m empty rows
+    assert oracle.nz_partition(np.zeros(6, np.int32), 4).tolist() == [[0, 0], [5, 0]]
+    # leading empty rows stay in the first piece; trailing ones in the last
+    rp = np.array([0, 0, 0, 4, 4, 8, 8, 8], np.int32)
+    assert oracle.nz_partition(rp, 4).tolist() == [[0, 0], [4, 4], [7, 8]]
+    assert oracle.nz_partition(rp, 2).tolist() == [[0, 0], [2, 2], [4, 4], [4, 6], [7, 8]]
+
+
 # ---------------------------------------------------------------- heuristic
 
 @pytest.mark.parametrize("m,nnz,merge", [

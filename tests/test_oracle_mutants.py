@@ -28,6 +28,9 @@ MUTANTS = {
     "sddmm_row_index": ("double g = or_load(dC, i * ldc + c, cdt);\n                double b",
                         "double g = or_load(dC, r * ldc + c, cdt);\n                double b"),
     "spmm_t_target": ("double* dst = dB + (int64_t)colind[p] * n;", "double* dst = dB + i * n;"),
+    "nz_search_strict": ("if ((int64_t)rowptr[mid + 1] <= j)", "if ((int64_t)rowptr[mid + 1] < j)"),
+    "nz_first_piece_searched": ("for (int64_t p = 1; p <= P; ++p) {", "for (int64_t p = 0; p <= P; ++p) {"),
+    "nz_parts_floor": ("int64_t P = (nnz + W - 1) / W;", "int64_t P = nnz / W;"),
     "heuristic_le": ("d < 9.35 ? 1 : 0", "d <= 9.35 ? 1 : 0"),
     "f16_exponent": ("e - 25", "e - 24"),
     "bf16_shift": ("<< 16;", "<< 15;"),
@@ -37,7 +40,7 @@ BATTERY = ["test_worked_example", "test_spmm_matches_dense_gemm", "test_identity
            "test_row_sum", "test_transpose_vs_scipy", "test_merge_walk_invariants",
            "test_merge_closed_forms", "test_heuristic_table", "test_bf16_and_f16_decoders",
            "test_gradients_euler", "test_spmm_t_and_sddmm_vs_dense", "test_semirings_brute_force",
-           "test_min_plus_bellman"]
+           "test_min_plus_bellman", "test_nz_partition"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
