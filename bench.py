@@ -151,7 +151,7 @@ def gcn_fwd_bwd(steps=20, warmup=3):
                      "fwd_gflops": round(2.0 * A.nnz * n / (fwd * 1e-3) / 1e9, 1),
                      "algorithmic_GBs": {"fwd": gbs(b_fwd, fwd), "dB": gbs(b_db, bwd_b),
                                          "dvals": gbs(b_dv, bwd_v)},
-                     "kernel": "merge" if plan.info().config.kernel else "rowsplit"}
+                     "kernel": nv.KERNEL_NAMES[plan.info().config.kernel]}
         plan.close()
     out["bf16_speedup_fwd_bwd"] = round(out["f32"]["fwd_bwd_ms"] / out["bf16"]["fwd_bwd_ms"], 3)
     out["bf16_speedup_fwd"] = round(out["f32"]["fwd_ms"] / out["bf16"]["fwd_ms"], 3)
@@ -233,8 +233,10 @@ def _best_of(nv, rp, ci, m, k, nnz, n, vals, Bt, C, kernel):
     candidate set restricted to that kernel)."""
     import torch
     best = None
-    if kernel == "merge":
-        shapes = [dict(kernel=1, items_per_wg=W, unroll=u) for W in (1024, 2048, 4096) for u in (2, 4, 8)]
+    if kernel in ("merge", "nzsplit"):
+        code = nv.SPMM_KERNEL_MERGE if kernel == "merge" else nv.SPMM_KERNEL_NZSPLIT
+        shapes = [dict(kernel=code, items_per_wg=W, unroll=u) for W in (1024, 2048, 4096)
+                  for u in (2, 4, 8)]
     else:
         shapes = [dict(kernel=0, lanes_per_row=l, unroll=u) for l in (0, 64, 32, 16, 8)
                   for u in (2, 4, 8)]
@@ -330,6 +332,57 @@ def heuristic_sweep(n=64):
                       "best_threshold_geomean_slowdown": round(loss(best_th), 3)}), flush=True)
 
 
+def nz_compare(n=64):
+    """The nonzero split (Sec. 4, scheme (a): equal nonzeros per piece, 1-D
+    search on row offsets) against the diagonal merge-path split and row
+    split, each at its fastest shape, on 1M x 1M matrices with 16M entries:
+    the power-law matrix of the headline, the same law on 10 % or 1 % of the
+    rows with the others empty (scattered), and one run of 900k empty rows
+    before 100k rows of 160 entries. Prints one JSON line per matrix."""
+    import torch
+    from paper_1803_08601_amd import native as nv
+    from paper_1803_08601_amd import workloads as wl
+    M = 1_000_000
+    rng = np.random.default_rng(1006)
+    cases = [("power law, no empty rows", None), ("power law on 10% of rows, rest empty", 0.10),
+             ("power law on 1% of rows, rest empty", 0.01),
+             ("900k empty rows, then 100k rows of 160", "run")]
+    for desc, frac in cases:
+        if frac is None:
+            A = wl.power_law(seed=1002)
+            rowptr, colind = A.rowptr, A.colind
+        else:
+            lengths = np.zeros(M, np.int64)
+            if frac == "run":
+                lengths[900_000:] = 160
+            else:
+                rows = np.sort(rng.choice(M, int(M * frac), replace=False))
+                lens, _ = wl.power_law_lengths(rng, rows.shape[0], mean=16.0 / frac, cap=100_000)
+                lengths[rows] = lens
+            colind = wl.distinct_sorted_columns(rng, lengths, M)
+            rowptr = wl.rowptr_from_lengths(lengths)
+        nnz = int(rowptr[-1])
+        rp = torch.from_numpy(rowptr).cuda()
+        ci = torch.from_numpy(colind).cuda()
+        g = torch.Generator(device="cuda")
+        g.manual_seed(13)
+        vals = torch.rand(nnz, generator=g, device="cuda") - 0.5
+        Bt = torch.rand(M, n, generator=g, device="cuda") - 0.5
+        C = torch.empty(M, n, device="cuda")
+        rec = {"matrix": desc, "m": M, "nnz": nnz, "n": n,
+               "empty_rows": int(np.count_nonzero(np.diff(rowptr) == 0))}
+        for kern in ("rowsplit", "merge", "nzsplit"):
+            best = _best_of(nv, rp, ci, M, M, nnz, n, vals, Bt, C, kern)
+            rec[f"{kern}_ms"] = round(best[0], 4)
+            rec[f"{kern}_shape"] = best[1]
+        plan = nv.Plan(rp, ci, M, M, n, nnz=nnz, mode="autotune")
+        rec["autotune_kernel"] = nv.KERNEL_NAMES[plan.info().config.kernel]
+        plan.close()
+        print(json.dumps(rec), flush=True)
+        del rp, ci, vals, Bt, C
+        torch.cuda.empty_cache()
+
+
 def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1)):
     """Sparse versus dense (Fig. 7): a 100k x 100k matrix with a fixed share
     of distinct random columns in every row times a 100k x 64 B, SpMM (plan by
@@ -397,7 +450,8 @@ def main():
     ap.add_argument("--workload", default="powerlaw", choices=["powerlaw", "stencil", "plain"])
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
-    ap.add_argument("--mode", default="autotune", choices=["autotune", "paper", "rowsplit", "merge"])
+    ap.add_argument("--mode", default="autotune",
+                    choices=["autotune", "paper", "rowsplit", "merge", "nzsplit", "rule"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true",
                     help="only the headline product (skip the GCN fwd+bwd and batched extras)")
@@ -405,6 +459,9 @@ def main():
                     help="run just one extra measurement and print its JSON (for profiling)")
     ap.add_argument("--sweep", action="store_true",
                     help="kernel-choice sweep over mean row length (re-derives the Sec. 5.4 threshold)")
+    ap.add_argument("--nzsplit", action="store_true",
+                    help="nonzero split against merge path and row split on matrices with "
+                         "runs of empty rows")
     ap.add_argument("--crossover", action="store_true",
                     help="sparse versus dense product over density (100k x 100k, n = 64)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -430,6 +487,9 @@ def main():
     if args.crossover:
         crossover(args.n)
         return
+    if args.nzsplit:
+        nz_compare(args.n)
+        return
     if args.copy_calibration:
         a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -453,7 +513,7 @@ def main():
     plan = nv.Plan(rp, ci, A.m, A.k, n, ld=n, dtype=nv.dtype_code(dt), mode=args.mode, nnz=A.nnz)
     plan_s = time.perf_counter() - t0
     info = plan.info()
-    kernel = "merge" if info.config.kernel == nv.SPMM_KERNEL_MERGE else "rowsplit"
+    kernel = nv.KERNEL_NAMES[info.config.kernel]
 
     ev = HipEvents()
     evb = [ev.create() for _ in range(args.steps)]
@@ -509,7 +569,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_merge" if kernel == "merge" else "k_rowsplit",
+                     "kernel": "k_rowsplit" if kernel == "rowsplit" else "k_merge",
                      "kernel_ms": round(kavg, 4), "algorithmic_bytes": bmin},
     }
     if not args.no_cpu_baseline:

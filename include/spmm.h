@@ -70,16 +70,30 @@ typedef enum spmm_dtype { SPMM_F32 = 0, SPMM_BF16 = 1, SPMM_F16 = 2 } spmm_dtype
  *              sweep (the Sec. 5.4 procedure on this GPU): merge-based when
  *              the mean row length is below 4 or the longest row has 4096
  *              or more entries (row split cannot spread one row over
- *              several workgroups), row split otherwise. */
+ *              several workgroups), row split otherwise.
+ *   NZSPLIT  : force the nonzero split (Sec. 4, scheme (a): the 1-D
+ *              partition the paper's merge-based kernel implements) with
+ *              default shapes. */
 typedef enum spmm_mode {
     SPMM_MODE_PAPER = 0,
     SPMM_MODE_AUTOTUNE = 1,
     SPMM_MODE_ROWSPLIT = 2,
     SPMM_MODE_MERGE = 3,
-    SPMM_MODE_RULE = 4
+    SPMM_MODE_RULE = 4,
+    SPMM_MODE_NZSPLIT = 5
 } spmm_mode;
 
-typedef enum spmm_kernel { SPMM_KERNEL_ROWSPLIT = 0, SPMM_KERNEL_MERGE = 1 } spmm_kernel;
+/* ROWSPLIT: Sec. 4.1. MERGE: merge-based, pieces cut on the diagonals of
+ * the merge path (2-D search; each piece holds items_per_wg rows plus
+ * nonzeros). NZSPLIT: merge-based, pieces cut by nonzero count (each piece
+ * holds items_per_wg nonzeros and however many row ends fall among them,
+ * found by a 1-D search on the row offsets): cheaper to partition, but a run
+ * of empty rows lands in one piece and is written by one lane group. */
+typedef enum spmm_kernel {
+    SPMM_KERNEL_ROWSPLIT = 0,
+    SPMM_KERNEL_MERGE = 1,
+    SPMM_KERNEL_NZSPLIT = 2
+} spmm_kernel;
 
 /* Semirings of spmm_execute_semiring: (add, multiply, identity). */
 typedef enum spmm_semiring {
@@ -98,7 +112,7 @@ typedef struct spmm_config {
                               a power of two from the lanes one B row needs up to 64 */
     int32_t unroll;        /* B-row gathers in flight per lane group: 1, 2, 4 or 8 */
     int32_t items_per_wg;  /* merge-based (Sec. 4.2): merge items (rows + nonzeros) per
-                              workgroup, 64 .. 8192 */
+                              workgroup, 64 .. 8192; NZSPLIT: nonzeros per workgroup */
     int32_t tile_cols;     /* columns per column tile (Fig. 3(a)'s 2-D grid): a multiple of
                               vec; the product runs over ceil(n / tile_cols) tiles, each
                               re-reading A but touching only its columns of B. 0 = as wide as
@@ -113,7 +127,7 @@ typedef struct spmm_plan_info {
     spmm_config config;    /* the shape that execute calls use */
     int32_t lanes_per_slot;/* lanes that cover one B row (or one 64*vec column tile) */
     int32_t col_tiles;     /* column tiles (grid y) */
-    int64_t num_parts;     /* merge-based: workgroups P (coordinates hold P + 1 pairs) */
+    int64_t num_parts;     /* MERGE / NZSPLIT: workgroups P (coordinates hold P + 1 pairs) */
     int64_t max_row_len;   /* longest row (from the device row statistics) */
     double mean_row_len;   /* nnz / m */
     double tuned_ms;       /* AUTOTUNE: median time of the chosen candidate, else 0 */
@@ -184,9 +198,11 @@ int spmm_execute_semiring(spmm_plan_t plan, int32_t semiring, const void* A_vals
 /* Plan facts for the host (sizes, the chosen config, Sec. 5.4 choice). */
 int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info_host);
 
-/* Merge-based plans: copy the P + 1 merge-path coordinates (i_p, j_p) for
- * diagonals min(p * W, m + nnz) into coords_host (2 * (P + 1) int32,
- * interleaved i, j). cap is the capacity in pairs. Synchronous.
+/* Merge-based plans: copy the P + 1 merge-path coordinates (i_p, j_p) that
+ * start the pieces into coords_host (2 * (P + 1) int32, interleaved i, j).
+ * MERGE: the states on diagonals min(p * W, m + nnz). NZSPLIT: (0, 0), then
+ * j_p = min(p * W, nnz) with i_p the number of rows whose end is <= j_p,
+ * and (m, nnz) last. cap is the capacity in pairs. Synchronous.
  * SPMM_ERR_STATE for row-split plans. */
 int spmm_plan_partition(spmm_plan_t plan, int32_t* coords_host, int64_t cap);
 

@@ -74,6 +74,7 @@ spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec) {
     s.ts_log2 = ilog2_ceil(lpr) - s.g_log2;
     s.unroll = p.cfg.unroll;
     s.W = p.cfg.items_per_wg;
+    s.nz = p.cfg.kernel == SPMM_KERNEL_NZSPLIT ? 1 : 0;
     return s;
 }
 
@@ -98,7 +99,7 @@ int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const vo
     int vec = p.cfg.vec;
     if (vec != 1 && (!aligned16(B) || !aligned16(C))) vec = 1;
     const spmmk::Shape s = resolve_shape(p, vec);
-    const bool merge = p.cfg.kernel == SPMM_KERNEL_MERGE;
+    const bool merge = p.cfg.kernel != SPMM_KERNEL_ROWSPLIT;
     if (merge && !p.ws.coords) return fail(SPMM_ERR_STATE, "merge plan without partition");
     const spmmk::ForwardArgs a{rowptr, colind, vals, B, C, p.m, p.n, p.ld,
                                p.ws.coords, p.ws.P, p.ws.carry_vals, p.ws.carry_rows};
@@ -118,9 +119,17 @@ static void free_ws(MergeWs& ws) {
     ws = MergeWs{};
 }
 
+// Pieces of the merge walk: diagonal pieces of W merge items, or (nonzero
+// split) pieces of W nonzeros, at least one when there are rows.
+static int64_t num_pieces(int64_t m, int64_t nnz, int W, bool nz) {
+    if (!nz) return (m + nnz + W - 1) / W;
+    if (m == 0) return 0;
+    return std::max<int64_t>(1, (nnz + W - 1) / W);
+}
+
 // Allocate (if needed) and fill the merge workspace for W items per piece.
-static int prepare_merge(const spmm_plan_s& p, MergeWs& ws, int W, hipStream_t st) {
-    const int64_t P = (p.m + p.nnz + W - 1) / W;
+static int prepare_merge(const spmm_plan_s& p, MergeWs& ws, int W, bool nz, hipStream_t st) {
+    const int64_t P = num_pieces(p.m, p.nnz, W, nz);
     if (P > ws.cap_P || p.n > ws.cap_n || !ws.coords) {
         free_ws(ws);
         const int64_t capP = std::max<int64_t>(P, 1);
@@ -132,7 +141,8 @@ static int prepare_merge(const spmm_plan_s& p, MergeWs& ws, int W, hipStream_t s
         ws.cap_n = capn;
     }
     ws.P = P;
-    hipError_t e = spmmk::launch_merge_partition(p.rowptr, p.m, p.nnz, W, P, ws.coords, st);
+    hipError_t e = spmmk::launch_merge_partition(p.rowptr, p.m, p.nnz, W, P, nz ? 1 : 0,
+                                                 ws.coords, st);
     if (e != hipSuccess) return hip_fail(e, "merge partition launch");
     return SPMM_OK;
 }
@@ -140,7 +150,8 @@ static int prepare_merge(const spmm_plan_s& p, MergeWs& ws, int W, hipStream_t s
 static int check_config(const spmm_plan_s& p, spmm_config& c) {
     const int v16 = vec16(p.dtype);
     const bool can16 = (p.n % v16 == 0) && (p.ld % v16 == 0);
-    if (c.kernel != SPMM_KERNEL_ROWSPLIT && c.kernel != SPMM_KERNEL_MERGE)
+    if (c.kernel != SPMM_KERNEL_ROWSPLIT && c.kernel != SPMM_KERNEL_MERGE &&
+        c.kernel != SPMM_KERNEL_NZSPLIT)
         return fail(SPMM_ERR_INVALID, "config.kernel %d is not a kernel", c.kernel);
     if (c.vec == 0) c.vec = can16 ? v16 : 1;
     if (c.vec != 1 && c.vec != v16)
@@ -174,14 +185,15 @@ static int check_config(const spmm_plan_s& p, spmm_config& c) {
     }
     if (c.items_per_wg < 64 || c.items_per_wg > 8192)
         return fail(SPMM_ERR_UNSUPPORTED, "config.items_per_wg %d outside 64..8192", c.items_per_wg);
-    if (c.kernel == SPMM_KERNEL_MERGE) {
+    if (c.kernel != SPMM_KERNEL_ROWSPLIT) {
         spmmk::Shape s;
         s.vec = c.vec;
         s.W = c.items_per_wg;
         if (spmmk::merge_lds_bytes(p.dtype, s) > lds_limit())
             return fail(SPMM_ERR_UNSUPPORTED, "items_per_wg %d needs more LDS than a workgroup has",
                         c.items_per_wg);
-        if ((p.m + p.nnz + c.items_per_wg - 1) / c.items_per_wg >= (int64_t(1) << 31))
+        if (num_pieces(p.m, p.nnz, c.items_per_wg, c.kernel == SPMM_KERNEL_NZSPLIT) >=
+            (int64_t(1) << 31))
             return fail(SPMM_ERR_UNSUPPORTED, "too many merge pieces");
     }
     return SPMM_OK;
@@ -222,6 +234,16 @@ static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_
         for (int W : {2048, 1024, 4096, 512})
             if (!max_W || W <= max_W)
                 for (int u : unrolls) out.push_back({SPMM_KERNEL_MERGE, vec, 1 << g_log2, u, W, tc});
+    }
+    // The nonzero split (the paper's own merge-based partition) after the
+    // diagonal one: within the tie margin the earlier candidate is kept.
+    for (int tc : tiles) {
+        int g_log2, nt;
+        slot_geometry(p.n, vec, &g_log2, &nt, tc);
+        for (int W : {2048, 1024})
+            if (!max_W || W <= max_W)
+                for (int u : unrolls)
+                    out.push_back({SPMM_KERNEL_NZSPLIT, vec, 1 << g_log2, u, W, tc});
     }
     for (int tc : tiles) {
         int g_log2, nt;
@@ -302,8 +324,8 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
         q.ws = MergeWs{};
         if (check_config(q, c) != SPMM_OK) continue;
         q.cfg = c;
-        if (c.kernel == SPMM_KERNEL_MERGE) {
-            rc = prepare_merge(q, ws, c.items_per_wg, st);
+        if (c.kernel != SPMM_KERNEL_ROWSPLIT) {
+            rc = prepare_merge(q, ws, c.items_per_wg, c.kernel == SPMM_KERNEL_NZSPLIT, st);
             if (rc != SPMM_OK) { cleanup(); return rc; }
             q.ws = ws;
         }
@@ -413,7 +435,7 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
     if (rc) return rc;
     if (dtype != SPMM_F32 && dtype != SPMM_BF16 && dtype != SPMM_F16)
         return fail(SPMM_ERR_UNSUPPORTED, "dtype %d", dtype);
-    if (!forced && (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_RULE))
+    if (!forced && (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_NZSPLIT))
         return fail(SPMM_ERR_INVALID, "mode %d", mode);
     if (m > 0 && !rowptr) return fail(SPMM_ERR_INVALID, "A_rowptr is NULL");
     if (nnz > 0 && !colind) return fail(SPMM_ERR_INVALID, "A_colind is NULL");
@@ -438,21 +460,24 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
         } else if (mode == SPMM_MODE_AUTOTUNE) {
             rc = autotune(*p, st, opts);
         } else {
-            const int kern = mode == SPMM_MODE_PAPER    ? p->paper_choice
-                             : mode == SPMM_MODE_RULE  ? rule_choice(*p)
-                             : mode == SPMM_MODE_MERGE ? SPMM_KERNEL_MERGE
-                                                        : SPMM_KERNEL_ROWSPLIT;
+            const int kern = mode == SPMM_MODE_PAPER     ? p->paper_choice
+                             : mode == SPMM_MODE_RULE    ? rule_choice(*p)
+                             : mode == SPMM_MODE_MERGE   ? SPMM_KERNEL_MERGE
+                             : mode == SPMM_MODE_NZSPLIT ? SPMM_KERNEL_NZSPLIT
+                                                          : SPMM_KERNEL_ROWSPLIT;
             p->cfg = spmm_config{kern, 0, 0, opts ? opts->fixed_unroll : 0, 0, 0};
             rc = check_config(*p, p->cfg);
         }
     }
     if (rc == SPMM_OK && opts && opts->max_W && p->cfg.items_per_wg > opts->max_W)
         p->cfg.items_per_wg = opts->max_W;
-    if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_MERGE)
-        rc = prepare_merge(*p, p->ws, p->cfg.items_per_wg, st);
-    // SDDMM walks merge pieces; a row-split plan gets a partition for it.
-    if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_ROWSPLIT && p->m > 0 && p->nnz > 0)
-        rc = prepare_merge(*p, p->sddmm_ws, kSddmmW, st);
+    if (rc == SPMM_OK && p->cfg.kernel != SPMM_KERNEL_ROWSPLIT)
+        rc = prepare_merge(*p, p->ws, p->cfg.items_per_wg, p->cfg.kernel == SPMM_KERNEL_NZSPLIT,
+                           st);
+    // SDDMM walks diagonal merge pieces (their row ends fit its LDS); other
+    // plans get such a partition for it.
+    if (rc == SPMM_OK && p->cfg.kernel != SPMM_KERNEL_MERGE && p->m > 0 && p->nnz > 0)
+        rc = prepare_merge(*p, p->sddmm_ws, kSddmmW, false, st);
     if (rc == SPMM_OK) {
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = hip_fail(e, "plan synchronise");
@@ -559,7 +584,7 @@ int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info) {
     const spmmk::Shape s = resolve_shape(*plan, plan->cfg.vec);
     info->lanes_per_slot = 1 << s.g_log2;
     info->col_tiles = s.col_tiles;
-    info->num_parts = plan->cfg.kernel == SPMM_KERNEL_MERGE ? plan->ws.P : 0;
+    info->num_parts = plan->cfg.kernel != SPMM_KERNEL_ROWSPLIT ? plan->ws.P : 0;
     info->max_row_len = plan->max_row_len;
     info->mean_row_len = plan->m ? double(plan->nnz) / double(plan->m) : 0.0;
     info->tuned_ms = plan->tuned_ms;
@@ -569,7 +594,7 @@ int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info) {
 
 int spmm_plan_partition(spmm_plan_t plan, int32_t* coords_host, int64_t cap) {
     if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
-    if (plan->cfg.kernel != SPMM_KERNEL_MERGE)
+    if (plan->cfg.kernel == SPMM_KERNEL_ROWSPLIT)
         return fail(SPMM_ERR_STATE, "row-split plan has no merge partition");
     if (!coords_host) return fail(SPMM_ERR_INVALID, "coords_host is NULL");
     if (cap < plan->ws.P + 1)

@@ -85,7 +85,7 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
     if (count > 0 && !problems_host) return fail(SPMM_ERR_INVALID, "problems is NULL");
     if (dtype != SPMM_F32 && dtype != SPMM_BF16 && dtype != SPMM_F16)
         return fail(SPMM_ERR_UNSUPPORTED, "dtype %d", dtype);
-    if (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_RULE) return fail(SPMM_ERR_INVALID, "mode %d", mode);
+    if (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_NZSPLIT) return fail(SPMM_ERR_INVALID, "mode %d", mode);
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     spmm_batch_s* b = new (std::nothrow) spmm_batch_s;
@@ -135,7 +135,7 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
         bp.rowptr = q.A_rowptr; bp.colind = q.A_colind; bp.vals = q.A_vals; bp.B = q.B; bp.C = q.C;
         bp.m = p.m; bp.ld = p.ld; bp.n = (int)p.n;
         bp.kernel = p.cfg.kernel; bp.vec = vec; bp.g_log2 = s.g_log2; bp.ts_log2 = s.ts_log2;
-        bp.W = s.W; bp.col_tiles = s.col_tiles;
+        bp.W = s.W; bp.col_tiles = s.col_tiles; bp.nz = s.nz;
         const double mean = double(p.nnz) / double(p.m);
         const double tile_cols = std::min<double>(double(p.n), double(vec << s.g_log2));
         Entry en{};
@@ -186,7 +186,7 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
         for (int i : bins[q]) {
             const Entry& w = work[i];
             const int pid = (int)probs.size();
-            if (w.bp.kernel == SPMM_KERNEL_MERGE && w.bp.P > 0) {
+            if (w.bp.kernel != SPMM_KERNEL_ROWSPLIT && w.bp.P > 0) {
                 merge_ids.push_back(pid);
                 piece_off.push_back(pieces);
                 pieces += w.bp.P;

@@ -70,14 +70,23 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchProb* __restrict__ 
                     rowsplit_block<S, S::kVec16, U>(p.rowptr, p.colind, vals, B, p.C, p.m, p.n,
                                                     p.ld, p.g_log2, p.ts_log2, t, w.coltile);
             } else {
-                if (p.vec == 1)
+                if (p.vec == 1 && !p.nz)
                     merge_tile<S, 1, U>(p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n, p.ld,
                                         p.g_log2, p.coords, p.W, p.carry_vals, p.carry_rows, t,
                                         w.coltile, smem);
-                else
+                else if (!p.nz)
                     merge_tile<S, S::kVec16, U>(p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n,
                                                 p.ld, p.g_log2, p.coords, p.W, p.carry_vals,
                                                 p.carry_rows, t, w.coltile, smem);
+                else if (p.vec == 1)
+                    merge_tile<S, 1, U, PlusTimes, true>(p.rowptr, p.colind, vals, B, p.C,
+                                                         (int)p.m, p.n, p.ld, p.g_log2, p.coords,
+                                                         p.W, p.carry_vals, p.carry_rows, t,
+                                                         w.coltile, smem);
+                else
+                    merge_tile<S, S::kVec16, U, PlusTimes, true>(
+                        p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n, p.ld, p.g_log2, p.coords,
+                        p.W, p.carry_vals, p.carry_rows, t, w.coltile, smem);
                 __syncthreads();  // LDS is reused by the next piece
             }
         }

@@ -37,13 +37,13 @@ struct BatchProb {
     int64_t m;
     int64_t ld;
     int n;
-    int kernel;   // 0 row split, 1 merge-based
+    int kernel;   // 0 row split, otherwise the merge walk
     int vec;
     int g_log2;
     int ts_log2;
     int W;
     int col_tiles;
-    int pad;
+    int nz;       // merge walk over nonzero-split pieces
     const int* coords;
     float* carry_vals;
     int* carry_rows;

@@ -18,8 +18,9 @@ struct Shape {
     int g_log2 = 0;
     int ts_log2 = 0;
     int unroll = 4;
-    int W = 1024;       // merge items per workgroup
+    int W = 1024;       // merge items per workgroup (nonzeros for the nonzero split)
     int col_tiles = 1;
+    int nz = 0;         // merge walk over nonzero-split pieces (1-D partition)
 };
 
 // Operands of one forward product; coords, P and the carry arrays are the
@@ -45,8 +46,10 @@ hipError_t launch_forward_plus_times(int dtype, bool merge, const Shape& s,
 hipError_t launch_forward_semiring(int semiring, int dtype, bool merge, const Shape& s,
                                    const ForwardArgs& a, hipStream_t st);
 
+// Piece start coordinates for the merge walk: diagonals of the merge path
+// (nz == 0) or the nonzero split (nz != 0).
 hipError_t launch_merge_partition(const int* rowptr, int64_t m, int64_t nnz, int W, int64_t P,
-                                  int* coords, hipStream_t st);
+                                  int nz, int* coords, hipStream_t st);
 
 // stats[0] = longest row, stats[1] = rows with >= 1024 entries,
 // stats[2] = 1 if rowptr is non-decreasing with rowptr[0] == 0 else 0.

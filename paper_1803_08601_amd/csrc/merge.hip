@@ -25,6 +25,31 @@ __global__ __launch_bounds__(kBlock) void k_merge_partition(const int* __restric
     coords[2 * p + 1] = (int)(d - lo);
 }
 
+// Nonzero split (Sec. 4, scheme (a)): piece p starts at nonzero
+// j = min(p * W, nnz) in the row found by a 1-D binary search on the row
+// offsets, i.e. after the i rows whose end is <= j (ties to the row end, as
+// on the merge path). Piece 0 starts at (0, 0), so it also takes the leading
+// empty rows, and piece P ends at (m, nnz).
+__global__ __launch_bounds__(kBlock) void k_nz_partition(const int* __restrict__ rowptr,
+                                                          int64_t m, int64_t nnz, int W,
+                                                          int64_t P, int* __restrict__ coords) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > P) return;
+    const int64_t j = p * W < nnz ? p * W : nnz;
+    int64_t lo = 0, hi = m;
+    if (p == 0) hi = 0;
+    if (p == P) lo = m;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)rowptr[mid + 1] <= j)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    coords[2 * p] = (int)lo;
+    coords[2 * p + 1] = (int)j;
+}
+
 size_t merge_lds_bytes(int dtype, const Shape& s) {
     (void)dtype;
     return (size_t)2 * kBlock * s.vec * sizeof(float) + (size_t)3 * s.W * sizeof(int) +
@@ -32,11 +57,15 @@ size_t merge_lds_bytes(int dtype, const Shape& s) {
 }
 
 hipError_t launch_merge_partition(const int* rowptr, int64_t m, int64_t nnz, int W, int64_t P,
-                                  int* coords, hipStream_t st) {
+                                  int nz, int* coords, hipStream_t st) {
     const int64_t threads = P + 1;
     const uint32_t grid = (uint32_t)((threads + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_merge_partition, dim3(grid), dim3(kBlock), 0, st, rowptr, m, nnz, W, P,
-                       coords);
+    if (nz)
+        hipLaunchKernelGGL(k_nz_partition, dim3(grid), dim3(kBlock), 0, st, rowptr, m, nnz, W, P,
+                           coords);
+    else
+        hipLaunchKernelGGL(k_merge_partition, dim3(grid), dim3(kBlock), 0, st, rowptr, m, nnz, W,
+                           P, coords);
     return hipGetLastError();
 }
 

@@ -199,11 +199,19 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
 // Every row is written exactly once by Phase 2 and updated at most once by
 // Phase 3; all sums run in an order fixed by (W, slot width), so results are
 // deterministic for a plan.
+//
+// Nonzero split (Sec. 4, scheme (a); nz != 0): the same walk over pieces cut
+// by nonzero count instead of by diagonal. A piece then holds W nonzeros and
+// any number of row ends; the row ends are staged in LDS when at most W of
+// them fall in the piece and read from global memory otherwise, and the
+// piece is split among its slots by nonzeros as well (a 1-D search on the
+// row ends), so a run of empty rows is emitted by one slot.
 
 // Phase 2 for merge piece `tile` and column tile `coltile`; smem holds
 // merge_lds_bytes() of LDS. Contains workgroup barriers: every thread of the
-// workgroup must call it with the same arguments.
-template <class S, int VEC, int U, class R = PlusTimes>
+// workgroup must call it with the same arguments. NZ selects nonzero-split
+// pieces.
+template <class S, int VEC, int U, class R = PlusTimes, bool NZ = false>
 __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
                                            const int* __restrict__ colind,
                                            const typename S::T* __restrict__ vals,
@@ -224,9 +232,17 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
     const int i0 = coords[2 * tile], j0 = coords[2 * tile + 1];
     const int i1 = coords[2 * tile + 2], j1 = coords[2 * tile + 3];
     const int nr = i1 - i0, nj = j1 - j0;
+    // Row ends local to the piece. A diagonal piece has nr + nj <= W items;
+    // a nonzero-split piece may hold more than W row ends (empty rows).
+    const bool rows_lds = !NZ || nr <= W;
+    auto rowend = [&](int r) -> int {
+        if constexpr (!NZ) return s_rowend[r];
+        return rows_lds ? s_rowend[r] : rowptr[i0 + 1 + r] - j0;
+    };
 
-    for (int t = threadIdx.x; t < nr; t += kBlock)
-        s_rowend[t] = __builtin_nontemporal_load(rowptr + i0 + 1 + t) - j0;
+    if (rows_lds)
+        for (int t = threadIdx.x; t < nr; t += kBlock)
+            s_rowend[t] = __builtin_nontemporal_load(rowptr + i0 + 1 + t) - j0;
     for (int t = threadIdx.x; t < nj; t += kBlock) {
         s_col[t] = __builtin_nontemporal_load(colind + j0 + t);
         s_val[t] = load_elem(vals + j0 + t, S{});
@@ -240,28 +256,52 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
 
     const int col = coltile * (VEC << g_log2) + g * VEC;
     const bool col_ok = col < n;
-    const int items = nr + nj;
-    const int ips = (items + NS - 1) / NS;
-    const int d0 = min(slot * ips, items), d1 = min(d0 + ips, items);
-    auto search = [&](int d) {
-        int lo = max(0, d - nj), hi = min(d, nr);
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_rowend[mid] + mid < d)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        return lo;
-    };
-    const int rs = search(d0), js = d0 - rs;
-    const int re = search(d1), je = d1 - re;
+    int rs, js, re, je;
+    if constexpr (!NZ) {
+        // even split of the piece's items by the diagonal search
+        const int items = nr + nj;
+        const int ips = (items + NS - 1) / NS;
+        const int d0 = min(slot * ips, items), d1 = min(d0 + ips, items);
+        auto search = [&](int d) {
+            int lo = max(0, d - nj), hi = min(d, nr);
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_rowend[mid] + mid < d)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            return lo;
+        };
+        rs = search(d0); js = d0 - rs;
+        re = search(d1); je = d1 - re;
+    } else {
+        // even split of the piece's nonzeros; a slot starts after the row
+        // ends at or before its first nonzero (the first slot at the piece
+        // start, which takes the piece's leading empty rows)
+        const int eps = (nj + NS - 1) / NS;
+        js = min(slot * eps, nj);
+        je = min(js + eps, nj);
+        auto ended_by = [&](int j) {
+            int lo = 0, hi = nr;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rowend(mid) <= j)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            return lo;
+        };
+        rs = slot == 0 ? 0 : ended_by(js);
+        re = ended_by(je);
+    }
 
     float acc[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] = R::zero();
     int r = rs;
-    int rend = r < nr ? s_rowend[r] : INT_MAX;
+    int rend = r < nr ? rowend(r) : INT_MAX;
     auto emit = [&]() {
         if (r == rs) {
             store_f32<VEC>(s_head + threadIdx.x * VEC, acc);
@@ -272,7 +312,7 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] = R::zero();
         ++r;
-        rend = r < nr ? s_rowend[r] : INT_MAX;
+        rend = r < nr ? rowend(r) : INT_MAX;
     };
 
     for (int jb = js; jb < je; jb += U) {
@@ -336,7 +376,7 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
     if (slot == NS - 1) {
         bool open = false;
         if (i1 < m) {
-            const int start_local = nr > 0 ? s_rowend[nr - 1] : rowptr[i0] - j0;
+            const int start_local = nr > 0 ? rowend(nr - 1) : rowptr[i0] - j0;
             open = nj > start_local;
         }
         if (open && col_ok) {
@@ -393,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsplit(const int* __restrict__ row
                                      blockIdx.y);
 }
 
-template <class S, int VEC, int U, class R>
+template <class S, int VEC, int U, class R, bool NZ>
 __global__ __launch_bounds__(kBlock) void k_merge(const int* __restrict__ rowptr,
                                                    const int* __restrict__ colind,
                                                    const typename S::T* __restrict__ vals,
@@ -403,8 +443,9 @@ __global__ __launch_bounds__(kBlock) void k_merge(const int* __restrict__ rowptr
                                                    int W, float* __restrict__ carry_vals,
                                                    int* __restrict__ carry_rows) {
     extern __shared__ __align__(16) unsigned char smem[];
-    merge_tile<S, VEC, U, R>(rowptr, colind, vals, B, C, m, n, ld, g_log2, coords, W, carry_vals,
-                             carry_rows, (int)xcd_remap(blockIdx.x, gridDim.x), blockIdx.y, smem);
+    merge_tile<S, VEC, U, R, NZ>(rowptr, colind, vals, B, C, m, n, ld, g_log2, coords, W,
+                                 carry_vals, carry_rows, (int)xcd_remap(blockIdx.x, gridDim.x),
+                                 blockIdx.y, smem);
 }
 
 template <class R>
@@ -430,9 +471,17 @@ hipError_t launch_one(bool merge, const Shape& s, const ForwardArgs& a, hipStrea
                            st, a.rowptr, a.colind, vals, B, a.C, a.m, (int)a.n, a.ld, s.g_log2,
                            s.ts_log2);
     } else {
-        hipLaunchKernelGGL((k_merge<S, VEC, U, R>), dim3((uint32_t)a.P, s.col_tiles), dim3(kBlock),
-                           merge_lds_bytes(0, s), st, a.rowptr, a.colind, vals, B, a.C, (int)a.m,
-                           (int)a.n, a.ld, s.g_log2, a.coords, s.W, a.carry_vals, a.carry_rows);
+        const dim3 grid((uint32_t)a.P, s.col_tiles);
+        if (s.nz)
+            hipLaunchKernelGGL((k_merge<S, VEC, U, R, true>), grid, dim3(kBlock),
+                               merge_lds_bytes(0, s), st, a.rowptr, a.colind, vals, B, a.C,
+                               (int)a.m, (int)a.n, a.ld, s.g_log2, a.coords, s.W, a.carry_vals,
+                               a.carry_rows);
+        else
+            hipLaunchKernelGGL((k_merge<S, VEC, U, R, false>), grid, dim3(kBlock),
+                               merge_lds_bytes(0, s), st, a.rowptr, a.colind, vals, B, a.C,
+                               (int)a.m, (int)a.n, a.ld, s.g_log2, a.coords, s.W, a.carry_vals,
+                               a.carry_rows);
     }
     return hipGetLastError();
 }

@@ -18,11 +18,15 @@ SPMM_OK, SPMM_ERR_INVALID, SPMM_ERR_UNSUPPORTED, SPMM_ERR_HIP, SPMM_ERR_NOMEM, S
     0, -1, -2, -3, -4, -5
 SPMM_F32, SPMM_BF16, SPMM_F16 = 0, 1, 2
 SPMM_MODE_PAPER, SPMM_MODE_AUTOTUNE, SPMM_MODE_ROWSPLIT, SPMM_MODE_MERGE, SPMM_MODE_RULE = 0, 1, 2, 3, 4
-SPMM_KERNEL_ROWSPLIT, SPMM_KERNEL_MERGE = 0, 1
+SPMM_MODE_NZSPLIT = 5
+SPMM_KERNEL_ROWSPLIT, SPMM_KERNEL_MERGE, SPMM_KERNEL_NZSPLIT = 0, 1, 2
 SPMM_PLUS_TIMES, SPMM_MIN_PLUS, SPMM_MAX_PLUS, SPMM_MAX_TIMES = 0, 1, 2, 3
 
 MODES = {"paper": SPMM_MODE_PAPER, "autotune": SPMM_MODE_AUTOTUNE,
-         "rowsplit": SPMM_MODE_ROWSPLIT, "merge": SPMM_MODE_MERGE, "rule": SPMM_MODE_RULE}
+         "rowsplit": SPMM_MODE_ROWSPLIT, "merge": SPMM_MODE_MERGE, "rule": SPMM_MODE_RULE,
+         "nzsplit": SPMM_MODE_NZSPLIT}
+KERNEL_NAMES = {SPMM_KERNEL_ROWSPLIT: "rowsplit", SPMM_KERNEL_MERGE: "merge",
+                SPMM_KERNEL_NZSPLIT: "nzsplit"}
 
 
 class spmm_config(ctypes.Structure):

@@ -13,7 +13,7 @@ from spmm_check import DT, TOL_F32, TOL_STORAGE_16, dev, host_bits, rel_err
 
 pytestmark = pytest.mark.gpu
 
-RS, MG = nv.SPMM_KERNEL_ROWSPLIT, nv.SPMM_KERNEL_MERGE
+RS, MG, NZ = nv.SPMM_KERNEL_ROWSPLIT, nv.SPMM_KERNEL_MERGE, nv.SPMM_KERNEL_NZSPLIT
 
 
 def make_plan(A, n, dtype="f32", kernel=None, mode="paper"):
@@ -81,13 +81,16 @@ def test_grad_b_and_vals_vs_oracle(dtype, name, n):
         assert rel_err(dv.cpu().numpy()[:A.nnz], r32, n32) <= TOL_STORAGE_16
 
 
-@pytest.mark.parametrize("kernel", [RS, MG])
-def test_backward_integer_exact(kernel):
+@pytest.mark.parametrize("kernel,mode", [(RS, "paper"), (MG, "paper"), (NZ, "paper"),
+                                         (None, "nzsplit")])
+def test_backward_integer_exact(kernel, mode):
+    """Integer data: dB and dvals bit for bit. With mode nzsplit the plan of
+    A^T uses the nonzero split too; SDDMM walks diagonal pieces either way."""
     A = wl.power_law(seed=9, m=20_000, cap=20_000, values="int")
     n = 32
     B = wl.dense(9, A.k, n, kind="int")
     dC = wl.dense(10, A.m, n, kind="int")
-    plan = make_plan(A, n, kernel=kernel)
+    plan = make_plan(A, n, kernel=kernel, mode=mode)
     plan.transpose_build()
     dB = torch.empty(A.k, n, device="cuda")
     dv = torch.empty(A.nnz, device="cuda")

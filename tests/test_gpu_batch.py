@@ -36,9 +36,11 @@ def build_batch(count, dtype, seed=1005, m_hi=6000, n_choices=(8, 32, 128), extr
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("mode", ["paper", "autotune", "merge", "rowsplit"])
+@pytest.mark.parametrize("mode", ["paper", "autotune", "merge", "rowsplit", "nzsplit"])
 def test_batch_graph_matches_solo_and_oracle(dtype, mode):
-    keep, probs = build_batch(40, dtype)
+    # one mostly empty matrix: nonzero-split pieces with more row ends than W
+    sparse = wl.random_csr(23, 20_000, 3_000, density=0.003, empty_frac=0.9)
+    keep, probs = build_batch(40, dtype, extra=[(sparse, 32)])
     h = nv.spmm_batch_plan(probs, nv.dtype_code(DT[dtype]), nv.MODES[mode])
     try:
         for C in (k[6] for k in keep):
@@ -61,6 +63,8 @@ def test_batch_graph_matches_solo_and_oracle(dtype, mode):
             assert kinds == {nv.SPMM_KERNEL_MERGE}
         if mode == "rowsplit":
             assert kinds == {nv.SPMM_KERNEL_ROWSPLIT}
+        if mode == "nzsplit":
+            assert kinds == {nv.SPMM_KERNEL_NZSPLIT}
     finally:
         nv.spmm_batch_destroy(h)
 

@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 
 RS = nv.SPMM_KERNEL_ROWSPLIT
 MG = nv.SPMM_KERNEL_MERGE
+NZ = nv.SPMM_KERNEL_NZSPLIT
 
 
 def _upload(A):
@@ -48,12 +49,20 @@ CONFIGS = [
     dict(kernel=MG, items_per_wg=4096, unroll=8),
     dict(kernel=RS, lanes_per_row=16, unroll=4, tile_cols=32),
     dict(kernel=MG, items_per_wg=512, unroll=4, tile_cols=32),
+    dict(kernel=NZ, items_per_wg=64, unroll=1),
+    dict(kernel=NZ, items_per_wg=256, unroll=2),
+    dict(kernel=NZ, items_per_wg=2048, unroll=4),
+    dict(kernel=NZ, items_per_wg=4096, unroll=8),
+    dict(kernel=NZ, items_per_wg=512, unroll=4, tile_cols=32),
 ]
 
 
-@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"{'rs' if c['kernel'] == 0 else 'mg'}-"
-                         f"{c.get('lanes_per_row', c.get('items_per_wg'))}-u{c['unroll']}"
-                         f"-t{c.get('tile_cols', 0)}")
+def cfg_id(c):
+    return (f"{nv.KERNEL_NAMES[c['kernel']]}-{c.get('lanes_per_row', c.get('items_per_wg'))}"
+            f"-u{c['unroll']}-t{c.get('tile_cols', 0)}")
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=cfg_id)
 @pytest.mark.parametrize("n", [1, 8, 32, 64, 100, 128, 512])
 def test_plain_configs(cfg, n):
     A = wl.plain(m=1000, k=900)
@@ -62,7 +71,7 @@ def test_plain_configs(cfg, n):
     check(A, dev(A.vals), dev(B), n, C)
 
 
-@pytest.mark.parametrize("mode", ["paper", "rowsplit", "merge", "autotune"])
+@pytest.mark.parametrize("mode", ["paper", "rowsplit", "merge", "nzsplit", "autotune"])
 def test_power_law_modes(mode):
     A = wl.power_law(seed=31, m=40_000, cap=20_000)
     for n in (8, 64):
@@ -73,9 +82,11 @@ def test_power_law_modes(mode):
         assert info.paper_choice == RS  # mean row length 16
         if mode == "merge":
             assert info.config.kernel == MG
+        if mode == "nzsplit":
+            assert info.config.kernel == NZ
 
 
-@pytest.mark.parametrize("mode", ["rowsplit", "merge"])
+@pytest.mark.parametrize("mode", ["rowsplit", "merge", "nzsplit"])
 def test_stencil_modes(mode):
     A = wl.stencil27(g=24)
     for n in (16, 128):
@@ -85,9 +96,7 @@ def test_stencil_modes(mode):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
-@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"{'rs' if c['kernel'] == 0 else 'mg'}-"
-                         f"{c.get('lanes_per_row', c.get('items_per_wg'))}-u{c['unroll']}"
-                         f"-t{c.get('tile_cols', 0)}")
+@pytest.mark.parametrize("cfg", CONFIGS, ids=cfg_id)
 def test_integer_exact(dtype, cfg):
     """Integer values: every partial sum is exact, so any summation order must
     reproduce the oracle bit for bit (catches dropped or doubled partials)."""
@@ -100,7 +109,7 @@ def test_integer_exact(dtype, cfg):
     assert np.array_equal(C.cpu().numpy().astype(np.float64), Cref)
 
 
-@pytest.mark.parametrize("kernel", [RS, MG])
+@pytest.mark.parametrize("kernel", [RS, MG, NZ])
 def test_identity_permutation_diagonal_bitwise(kernel):
     k, n = 3000, 32
     rng = np.random.default_rng(0)
@@ -124,10 +133,39 @@ def test_merge_partition_bit_exact(W):
     assert np.array_equal(got, oracle.merge_partition(A.rowptr, W))
 
 
+NZ_MATRICES = {
+    "power_law": wl.power_law(seed=8, m=20_000, cap=10_000),
+    "mostly_empty": wl.random_csr(21, 30_000, 5_000, density=0.002, empty_frac=0.95),
+    "leading_trailing_empty": wl.CSR(np.array([0] * 700 + list(range(0, 3001, 3)) + [3000] * 900,
+                                              np.int32),
+                                     np.random.default_rng(3).integers(0, 400, 3000).astype(np.int32),
+                                     np.random.default_rng(4).uniform(-1, 1, 3000).astype(np.float32),
+                                     700 + 1000 + 900, 400),
+    "no_entries": wl.random_csr(22, 5_000, 100, density=0.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NZ_MATRICES))
+@pytest.mark.parametrize("W", [64, 100, 1024, 4096])
+def test_nz_partition_bit_exact_and_product(name, W):
+    """Nonzero-split coordinates equal the oracle's bit for bit; the product
+    is right also where a piece holds more than W row ends (runs of empty
+    rows, whose ends the kernel reads from global memory instead of LDS)."""
+    A = NZ_MATRICES[name]
+    n = 24
+    B = wl.dense(8, A.k, n)
+    C, plan = run(A, dev(A.vals), dev(B), n, config=dict(kernel=NZ, items_per_wg=W))
+    got = plan.partition()
+    want = oracle.nz_partition(A.rowptr, W)
+    assert np.array_equal(got, want)
+    assert plan.info().num_parts == want.shape[0] - 1
+    check(A, dev(A.vals), dev(B), n, C)
+
+
 def test_row_sum_invariant_and_determinism():
     A = wl.power_law(seed=12, m=20_000, cap=20_000, values="uniform")
     ones = np.ones((A.k, 32), np.float32)
-    for cfg in (dict(kernel=RS), dict(kernel=MG, items_per_wg=512)):
+    for cfg in (dict(kernel=RS), dict(kernel=MG, items_per_wg=512), dict(kernel=NZ, items_per_wg=512)):
         C1, plan = run(A, dev(A.vals), dev(ones), 32, config=cfg)
         C2 = torch.empty_like(C1)
         plan.execute(dev(A.vals), dev(ones), C2)
@@ -157,7 +195,7 @@ EDGE = {
 
 
 @pytest.mark.parametrize("name", sorted(EDGE))
-@pytest.mark.parametrize("kernel", [RS, MG])
+@pytest.mark.parametrize("kernel", [RS, MG, NZ])
 @pytest.mark.parametrize("n", [3, 16, 260])
 def test_edge_cases(name, kernel, n):
     A = EDGE[name]
@@ -166,7 +204,7 @@ def test_edge_cases(name, kernel, n):
     check(A, dev(A.vals), dev(B), n, C)
 
 
-@pytest.mark.parametrize("kernel", [RS, MG])
+@pytest.mark.parametrize("kernel", [RS, MG, NZ])
 def test_ld_padding_and_unaligned(kernel):
     A = wl.power_law(seed=13, m=5000, cap=2000)
     n, ld = 24, 40
@@ -191,7 +229,7 @@ def test_ld_padding_and_unaligned(kernel):
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
-@pytest.mark.parametrize("kernel", [RS, MG])
+@pytest.mark.parametrize("kernel", [RS, MG, NZ])
 def test_half_storage_errors(dtype, kernel):
     """Kernel error against the oracle on the rounded inputs (1e-5) and
     storage error against the original fp32 inputs (1e-2)."""
