@@ -72,6 +72,12 @@ def bytes_min(m, k, nnz, n, sv, sb):
     return 4 * (m + 1) + (4 + sv) * nnz + sb * k * n + 4 * m * n
 
 
+def bytes_gather(m, nnz, n, sv, sb):
+    """Traffic of the gather model of Table 1: as bytes_min, but every entry
+    fetches its B row (no reuse of B rows on chip)."""
+    return 4 * (m + 1) + (4 + sv) * nnz + sb * nnz * n + 4 * m * n
+
+
 def make_workload(name, n):
     from paper_1803_08601_amd import workloads as wl
     if name == "powerlaw":
@@ -336,7 +342,8 @@ def nz_compare(n=64):
     """The nonzero split (Sec. 4, scheme (a): equal nonzeros per piece, 1-D
     search on row offsets) against the diagonal merge-path split and row
     split, each at its fastest shape, on 1M x 1M matrices with 16M entries:
-    the power-law matrix of the headline, the same law on 10 % or 1 % of the
+    uniform rows of 16 random columns (the same gathers without any
+    irregularity), the power-law matrix of the headline, the same law on 10 % or 1 % of the
     rows with the others empty (scattered), and one run of 900k empty rows
     before 100k rows of 160 entries. Prints one JSON line per matrix."""
     import torch
@@ -344,7 +351,8 @@ def nz_compare(n=64):
     from paper_1803_08601_amd import workloads as wl
     M = 1_000_000
     rng = np.random.default_rng(1006)
-    cases = [("power law, no empty rows", None), ("power law on 10% of rows, rest empty", 0.10),
+    cases = [("uniform rows of 16 (no irregularity)", "uniform"),
+             ("power law, no empty rows", None), ("power law on 10% of rows, rest empty", 0.10),
              ("power law on 1% of rows, rest empty", 0.01),
              ("900k empty rows, then 100k rows of 160", "run")]
     for desc, frac in cases:
@@ -353,7 +361,9 @@ def nz_compare(n=64):
             rowptr, colind = A.rowptr, A.colind
         else:
             lengths = np.zeros(M, np.int64)
-            if frac == "run":
+            if frac == "uniform":
+                lengths[:] = 16
+            elif frac == "run":
                 lengths[900_000:] = 160
             else:
                 rows = np.sort(rng.choice(M, int(M * frac), replace=False))
@@ -536,6 +546,7 @@ def main():
     gflops = flops / (ms * 1e-3) / 1e9
     sv = sb = torch.tensor([], dtype=dt).element_size()
     bmin = bytes_min(A.m, A.k, A.nnz, n, sv, sb)
+    bgat = bytes_gather(A.m, A.nnz, n, sv, sb)
     kavg = float(np.mean(kern_ms))
     achieved = bmin / (kavg * 1e-3) / 1e9
 
@@ -570,7 +581,10 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel": "k_rowsplit" if kernel == "rowsplit" else "k_merge",
-                     "kernel_ms": round(kavg, 4), "algorithmic_bytes": bmin},
+                     "kernel_ms": round(kavg, 4), "algorithmic_bytes": bmin,
+                     "gather_model": {"bytes": bgat,
+                                      "achieved": round(bgat / (kavg * 1e-3) / 1e9, 1),
+                                      "frac": round(bgat / (kavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, n)

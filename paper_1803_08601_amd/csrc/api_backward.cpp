@@ -22,11 +22,12 @@ int spmm_transpose_build(spmm_plan_t plan, void* stream) {
     hipStream_t st = static_cast<hipStream_t>(stream);
     spmm_plan_s& p = *plan;
     Transpose& tr = p.tr;
-    int *k0 = nullptr, *k1 = nullptr, *v1 = nullptr, *hist = nullptr;
+    int *k0 = nullptr, *k1 = nullptr, *v1 = nullptr, *r0 = nullptr, *hist = nullptr;
     auto free_tmp = [&]() {
         if (k0) (void)hipFree(k0);
         if (k1) (void)hipFree(k1);
         if (v1) (void)hipFree(v1);
+        if (r0) (void)hipFree(r0);
         if (hist) (void)hipFree(hist);
     };
     auto free_tr = [&]() {
@@ -43,12 +44,13 @@ int spmm_transpose_build(spmm_plan_t plan, void* stream) {
     if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&k0, sizeof(int) * p.nnz);
     if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&k1, sizeof(int) * p.nnz);
     if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&v1, sizeof(int) * p.nnz);
+    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&r0, sizeof(int) * p.nnz);
     if (e == hipSuccess && p.nnz > 0)
-        e = hipMalloc(&hist, sizeof(int) * spmmk::transpose_hist_len(p.nnz));
+        e = hipMalloc(&hist, sizeof(int) * spmmk::transpose_scratch_len(p.nnz));
     if (e == hipSuccess) {
         if (p.nnz > 0)
             e = spmmk::transpose_build(p.rowptr, p.colind, p.m, p.k, p.nnz, tr.at_rowptr,
-                                       tr.at_colind, tr.perm, k0, k1, v1, hist, st);
+                                       tr.at_colind, tr.perm, k0, k1, v1, r0, hist, st);
         else
             e = hipMemsetAsync(tr.at_rowptr, 0, sizeof(int) * (p.k + 1), st);
     }

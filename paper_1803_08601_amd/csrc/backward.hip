@@ -27,6 +27,7 @@ __global__ __launch_bounds__(kWave) void k_radix_hist(const int* __restrict__ ke
     for (int d = threadIdx.x; d < kRadix; d += kWave) cnt[d] = 0;
     __syncthreads();
     const int64_t base = t * kSortTile;
+#pragma unroll 8
     for (int r = 0; r < kSortRounds; ++r) {
         const int64_t i = base + r * kWave + threadIdx.x;
         if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadix - 1)], 1);
@@ -35,8 +36,53 @@ __global__ __launch_bounds__(kWave) void k_radix_hist(const int* __restrict__ ke
     for (int d = threadIdx.x; d < kRadix; d += kWave) hist[(int64_t)d * ntiles + t] = cnt[d];
 }
 
+// Device-wide exclusive scan of int32 in place, in three launches: per-chunk
+// sums, a scan of the chunk sums by one workgroup, and the scan of each chunk
+// from its offset. A chunk is kScanPer consecutive items per thread of a
+// 256-thread workgroup.
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kBlock * kScanPer;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* s_wave, int* total) {
+    // inclusive scan within the wavefront, then across the four wavefronts
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) s_wave[w] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / kWave; ++q) {
+        const int sw = s_wave[q];
+        before += q < w ? sw : 0;
+        all += sw;
+    }
+    *total = all;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_sums(const int* __restrict__ a, int64_t len,
+                                                       int* __restrict__ sums) {
+    __shared__ int s_wave[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    int v = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        const int64_t i = base + q * kBlock + threadIdx.x;  // coalesced; order is irrelevant
+        if (i < len) v += a[i];
+    }
+    int total;
+    (void)block_exclusive_scan(v, s_wave, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
 // Exclusive scan of `len` ints in place by one workgroup of 1024 threads:
-// each thread scans a contiguous chunk, chunk sums are scanned in LDS.
+// each thread scans a contiguous chunk, chunk sums are scanned in LDS. Used
+// for the chunk sums (a few thousand at most for any int32 entry count).
 __global__ __launch_bounds__(1024) void k_scan_single(int* __restrict__ a, int64_t len) {
     __shared__ int sums[1024];
     const int64_t per = (len + 1023) / 1024;
@@ -60,29 +106,72 @@ __global__ __launch_bounds__(1024) void k_scan_single(int* __restrict__ a, int64
     }
 }
 
-// Stable scatter of one digit pass. One wavefront walks its tile in rounds of
-// 64 consecutive items; within a round, lanes holding the same digit find
-// each other with 8 ballots and take ranks in lane order, so item order is
-// kept within the tile; tiles are placed in order by the scanned counts.
+__global__ __launch_bounds__(kBlock) void k_scan_chunks(int* __restrict__ a, int64_t len,
+                                                         const int* __restrict__ offs) {
+    __shared__ int s_wave[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        v[q] = base + q < len ? a[base + q] : 0;
+        sum += v[q];
+    }
+    int total;
+    int run = offs[blockIdx.x] + block_exclusive_scan(sum, s_wave, &total);
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        if (base + q < len) a[base + q] = run;
+        run += v[q];
+    }
+}
+
+int64_t scan_chunks(int64_t len) { return (len + kScanChunk - 1) / kScanChunk; }
+
+static hipError_t exclusive_scan(int* a, int64_t len, int* sums, hipStream_t st) {
+    const int64_t nb = scan_chunks(len);
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_sums, dim3((uint32_t)nb), dim3(kBlock), 0, st, a, len, sums);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, sums, nb);
+    hipLaunchKernelGGL(k_scan_chunks, dim3((uint32_t)nb), dim3(kBlock), 0, st, a, len, sums);
+    return hipGetLastError();
+}
+
+// Stable scatter of one digit pass, carrying two value arrays (entry
+// position and row of A). One wavefront walks its tile in rounds of 64
+// consecutive items, with the whole tile's keys and values loaded up front;
+// within a round, lanes holding the same digit find each other with 8
+// ballots and take ranks in lane order, so item order is kept within the
+// tile; tiles are placed in order by the scanned counts.
 __global__ __launch_bounds__(kWave) void k_radix_scatter(const int* __restrict__ keys_in,
                                                           const int* __restrict__ vals_in,
+                                                          const int* __restrict__ rows_in,
                                                           int* __restrict__ keys_out,
-                                                          int* __restrict__ vals_out, int64_t n,
+                                                          int* __restrict__ vals_out,
+                                                          int* __restrict__ rows_out, int64_t n,
                                                           int shift, int64_t ntiles,
                                                           const int* __restrict__ offs) {
     __shared__ int next[kRadix];
     const int64_t t = blockIdx.x;
     const int lane = threadIdx.x;
     for (int d = lane; d < kRadix; d += kWave) next[d] = offs[(int64_t)d * ntiles + t];
-    __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = t * kSortTile;
+    int key[kSortRounds], val[kSortRounds], row[kSortRounds];
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         const int64_t i = base + r * kWave + lane;
         const bool ok = i < n;
-        const int key = ok ? keys_in[i] : 0;
-        const int val = ok ? vals_in[i] : 0;
-        const int d = (key >> shift) & (kRadix - 1);
+        key[r] = ok ? keys_in[i] : 0;
+        val[r] = ok ? vals_in[i] : 0;
+        row[r] = ok ? rows_in[i] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + r * kWave + lane;
+        const bool ok = i < n;
+        const int d = (key[r] >> shift) & (kRadix - 1);
         uint64_t match = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
@@ -93,8 +182,9 @@ __global__ __launch_bounds__(kWave) void k_radix_scatter(const int* __restrict__
         const int pos = ok ? next[d] + rank : 0;
         __syncthreads();
         if (ok) {
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+            keys_out[pos] = key[r];
+            vals_out[pos] = val[r];
+            rows_out[pos] = row[r];
             // the highest lane of each digit group advances that digit's cursor
             if ((match >> lane) == 1ull) next[d] = pos + 1;
         }
@@ -122,20 +212,16 @@ __global__ __launch_bounds__(kBlock) void k_lower_bounds(const int* __restrict__
     }
 }
 
-// AT_colind[q] = the row of A holding entry perm[q]: the last i with
-// rowptr[i] <= perm[q].
-__global__ __launch_bounds__(kBlock) void k_rows_of(const int* __restrict__ rowptr, int64_t m,
-                                                     const int* __restrict__ perm, int64_t n,
-                                                     int* __restrict__ out) {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int p = perm[q];
-        int64_t lo = 0, hi = m;  // find largest i in [0, m) with rowptr[i] <= p
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (rowptr[mid] <= p) lo = mid; else hi = mid - 1;
-        }
-        out[q] = (int)lo;
+// rows[p] = the row of A holding entry p: one wavefront per row, its lanes
+// writing the row's entries 64 at a time.
+__global__ __launch_bounds__(kBlock) void k_row_ids(const int* __restrict__ rowptr, int64_t m,
+                                                     int* __restrict__ rows) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < m;
+         i += nw) {
+        const int lo = rowptr[i], hi = rowptr[i + 1];
+        for (int j = lo + lane; j < hi; j += kWave) rows[j] = (int)i;
     }
 }
 
@@ -160,39 +246,53 @@ static uint32_t grid_for(int64_t n, int64_t cap = 65536) {
 
 hipError_t transpose_build(const int* rowptr, const int* colind, int64_t m, int64_t k,
                            int64_t nnz, int* at_rowptr, int* at_colind, int* perm,
-                           int* tmp_keys0, int* tmp_keys1, int* tmp_vals1, int* hist,
-                           hipStream_t st) {
-    // keys: column indices; values: entry positions (perm ends up in `perm`)
+                           int* tmp_keys0, int* tmp_keys1, int* tmp_vals1, int* tmp_rows0,
+                           int* scratch, hipStream_t st) {
+    // keys: column indices; values: entry positions (end in `perm`) and rows
+    // of A (end in `at_colind`)
     hipError_t e = hipMemcpyAsync(tmp_keys0, colind, sizeof(int) * nnz, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_iota, dim3(grid_for(nnz)), dim3(kBlock), 0, st, perm, nnz);
+    hipLaunchKernelGGL(k_row_ids, dim3(grid_for(m * kWave)), dim3(kBlock), 0, st, rowptr, m,
+                       tmp_rows0);
     int bits = 0;
     while (bits < 31 && (int64_t(1) << bits) < k) ++bits;
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     const int64_t ntiles = (nnz + kSortTile - 1) / kSortTile;
+    const int64_t hlen = ntiles * kRadix;
+    int* hist = scratch;
+    int* sums = scratch + hlen;
     int *kin = tmp_keys0, *kout = tmp_keys1, *vin = perm, *vout = tmp_vals1;
+    int *rin = tmp_rows0, *rout = at_colind;
     for (int ps = 0; ps < passes; ++ps) {
         const int shift = ps * kRadixBits;
         hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)ntiles), dim3(kWave), 0, st, kin, nnz,
                            shift, ntiles, hist);
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, hist, ntiles * kRadix);
+        e = exclusive_scan(hist, hlen, sums, st);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)ntiles), dim3(kWave), 0, st, kin, vin,
-                           kout, vout, nnz, shift, ntiles, hist);
+                           rin, kout, vout, rout, nnz, shift, ntiles, hist);
         int* tk = kin; kin = kout; kout = tk;
         int* tv = vin; vin = vout; vout = tv;
+        int* tr = rin; rin = rout; rout = tr;
     }
     if (vin != perm) {
         e = hipMemcpyAsync(perm, vin, sizeof(int) * nnz, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
+    if (rin != at_colind) {
+        e = hipMemcpyAsync(at_colind, rin, sizeof(int) * nnz, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_lower_bounds, dim3(grid_for(k + 1)), dim3(kBlock), 0, st, kin, nnz, k,
                        at_rowptr);
-    hipLaunchKernelGGL(k_rows_of, dim3(grid_for(nnz)), dim3(kBlock), 0, st, rowptr, m, perm, nnz,
-                       at_colind);
     return hipGetLastError();
 }
 
-int64_t transpose_hist_len(int64_t nnz) { return ((nnz + kSortTile - 1) / kSortTile) * kRadix; }
+int64_t transpose_scratch_len(int64_t nnz) {
+    const int64_t hlen = ((nnz + kSortTile - 1) / kSortTile) * kRadix;
+    return hlen + scan_chunks(hlen);
+}
 
 hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int64_t n,
                                float* out, hipStream_t st) {

@@ -111,18 +111,20 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchProb* __restrict__ 
 
 // Phase 3 of every merge-based problem: piece g of the concatenated piece
 // list belongs to the last merge problem whose first piece is <= g.
-__global__ __launch_bounds__(kWave) void k_batch_fixup(const BatchProb* __restrict__ probs,
-                                                        const int* __restrict__ merge_ids,
-                                                        const int64_t* __restrict__ piece_off,
-                                                        int nmerge) {
-    const int64_t gp = blockIdx.x;
+__global__ __launch_bounds__(kBlock) void k_batch_fixup(const BatchProb* __restrict__ probs,
+                                                         const int* __restrict__ merge_ids,
+                                                         const int64_t* __restrict__ piece_off,
+                                                         int nmerge, int64_t total_pieces) {
+    const int64_t gp = (int64_t)blockIdx.x * kFixupWaves + threadIdx.x / kWave;
+    if (gp >= total_pieces) return;
     int lo = 0, hi = nmerge - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (piece_off[mid] <= gp) lo = mid; else hi = mid - 1;
     }
     const BatchProb& p = probs[merge_ids[lo]];
-    merge_fixup_piece(p.C, p.ld, p.n, p.carry_vals, p.carry_rows, p.P, gp - piece_off[lo]);
+    merge_fixup_piece(p.C, p.ld, p.n, p.carry_vals, p.carry_rows, p.P, gp - piece_off[lo],
+                      threadIdx.x & (kWave - 1));
 }
 
 template <class S, int U>
@@ -170,8 +172,10 @@ hipError_t launch_batch(int dtype, int grid, size_t lds, const BatchProb* probs,
         }
     }
     if (nmerge > 0 && total_pieces > 0)
-        hipLaunchKernelGGL(k_batch_fixup, dim3((uint32_t)total_pieces), dim3(kWave), 0, st, probs,
-                           merge_ids, piece_off, nmerge);
+        hipLaunchKernelGGL(k_batch_fixup,
+                           dim3((uint32_t)((total_pieces + kFixupWaves - 1) / kFixupWaves)),
+                           dim3(kBlock), 0, st, probs, merge_ids, piece_off, nmerge,
+                           total_pieces);
     return hipGetLastError();
 }
 

@@ -61,13 +61,14 @@ hipError_t launch_check_cols(const int* colind, int64_t nnz, int64_t k, int* fla
 
 size_t merge_lds_bytes(int dtype, const Shape& s);
 
-// CSR of A^T by a stable radix sort of (column, entry) pairs. Scratch:
-// tmp_keys0/tmp_keys1/tmp_vals1 of nnz ints, hist of transpose_hist_len(nnz).
+// CSR of A^T by a stable radix sort of (column, entry) pairs that carries
+// each entry's row of A along. Scratch: tmp_keys0/tmp_keys1/tmp_vals1/
+// tmp_rows0 of nnz ints, scratch of transpose_scratch_len(nnz) ints.
 hipError_t transpose_build(const int* rowptr, const int* colind, int64_t m, int64_t k,
                            int64_t nnz, int* at_rowptr, int* at_colind, int* perm,
-                           int* tmp_keys0, int* tmp_keys1, int* tmp_vals1, int* hist,
-                           hipStream_t st);
-int64_t transpose_hist_len(int64_t nnz);
+                           int* tmp_keys0, int* tmp_keys1, int* tmp_vals1, int* tmp_rows0,
+                           int* scratch, hipStream_t st);
+int64_t transpose_scratch_len(int64_t nnz);
 
 // out[q] = widen(vals[perm[q]]) for q < n.
 hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int64_t n,

@@ -399,20 +399,48 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
 
 // Phase 3 for piece p: the first piece of every run of pieces that carry
 // into the same row adds the run's carry-outs (in piece order) to that row of
-// C. One wavefront.
+// C. One wavefront per piece (lane = its lane index). The row ids of the
+// piece and its neighbours are loaded together; a long run (a row spanning
+// many pieces) is measured 64 pieces per round with a ballot and summed with
+// eight carry-outs in flight, so its cost grows by one memory round trip per
+// 64 pieces and per 8 pieces instead of two per piece.
+constexpr int kFixupWaves = kBlock / kWave;  // pieces per fix-up workgroup
+constexpr int kFixupBatch = 8;               // carry-outs in flight per lane
+
 template <class R = PlusTimes>
 __device__ __forceinline__ void merge_fixup_piece(float* __restrict__ C, int64_t ld, int n,
                                                   const float* __restrict__ carry_vals,
                                                   const int* __restrict__ carry_rows, int64_t P,
-                                                  int64_t p) {
+                                                  int64_t p, int lane) {
+    if (p >= P) return;
     const int r = carry_rows[p];
-    if (r < 0) return;
-    if (p > 0 && carry_rows[p - 1] == r) return;
+    const int rprev = carry_rows[p > 0 ? p - 1 : 0];
+    const int rnext = carry_rows[p + 1 < P ? p + 1 : p];
+    if (r < 0 || (p > 0 && rprev == r)) return;
     int64_t q_end = p + 1;
-    while (q_end < P && carry_rows[q_end] == r) ++q_end;
-    for (int c = threadIdx.x; c < n; c += kWave) {
+    if (p + 1 < P && rnext == r) {
+        q_end = p + 2;
+        for (;;) {  // first piece at or after q_end that carries elsewhere
+            const int64_t q = q_end + lane;
+            const uint64_t other = __ballot(q >= P || carry_rows[q] != r);
+            if (other) {
+                q_end += __ffsll((unsigned long long)other) - 1;
+                break;
+            }
+            q_end += kWave;
+        }
+    }
+    for (int c = lane; c < n; c += kWave) {
         float s = R::zero();
-        for (int64_t q = p; q < q_end; ++q) s = R::add(s, carry_vals[q * n + c]);
+        for (int64_t q = p; q < q_end; q += kFixupBatch) {
+            float t[kFixupBatch];
+#pragma unroll
+            for (int u = 0; u < kFixupBatch; ++u)
+                t[u] = q + u < q_end ? carry_vals[(q + u) * n + c] : 0.f;
+#pragma unroll
+            for (int u = 0; u < kFixupBatch; ++u)
+                if (q + u < q_end) s = R::add(s, t[u]);
+        }
         C[(int64_t)r * ld + c] = R::add(C[(int64_t)r * ld + c], s);
     }
 }
@@ -449,11 +477,12 @@ __global__ __launch_bounds__(kBlock) void k_merge(const int* __restrict__ rowptr
 }
 
 template <class R>
-__global__ __launch_bounds__(kWave) void k_merge_fixup(float* __restrict__ C, int64_t ld, int n,
-                                                        const float* __restrict__ carry_vals,
-                                                        const int* __restrict__ carry_rows,
-                                                        int64_t P) {
-    merge_fixup_piece<R>(C, ld, n, carry_vals, carry_rows, P, blockIdx.x);
+__global__ __launch_bounds__(kBlock) void k_merge_fixup(float* __restrict__ C, int64_t ld, int n,
+                                                         const float* __restrict__ carry_vals,
+                                                         const int* __restrict__ carry_rows,
+                                                         int64_t P) {
+    const int64_t p = (int64_t)blockIdx.x * kFixupWaves + threadIdx.x / kWave;
+    merge_fixup_piece<R>(C, ld, n, carry_vals, carry_rows, P, p, threadIdx.x & (kWave - 1));
 }
 
 // Host-side dispatch over storage type, vector width and unroll for one
@@ -525,7 +554,8 @@ hipError_t launch_forward(int dtype, bool merge, const Shape& s, const ForwardAr
         if (e != hipSuccess) return e;
     }
     if (merge && a.n > 0) {
-        hipLaunchKernelGGL((k_merge_fixup<R>), dim3((uint32_t)a.P), dim3(kWave), 0, st, a.C, a.ld,
+        const uint32_t groups = (uint32_t)((a.P + kFixupWaves - 1) / kFixupWaves);
+        hipLaunchKernelGGL((k_merge_fixup<R>), dim3(groups), dim3(kBlock), 0, st, a.C, a.ld,
                            (int)a.n, a.carry_vals, a.carry_rows, a.P);
         e = hipGetLastError();
     }
