@@ -462,6 +462,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--mode", default="autotune",
                     choices=["autotune", "paper", "rowsplit", "merge", "nzsplit", "rule"])
+    ap.add_argument("--config", default=None,
+                    help="force a kernel shape, JSON of spmm_config fields, e.g. "
+                         "'{\"kernel\": 1, \"items_per_wg\": 2048, \"unroll\": 2}'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true",
                     help="only the headline product (skip the GCN fwd+bwd and batched extras)")
@@ -520,7 +523,9 @@ def main():
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
-    plan = nv.Plan(rp, ci, A.m, A.k, n, ld=n, dtype=nv.dtype_code(dt), mode=args.mode, nnz=A.nnz)
+    cfg = json.loads(args.config) if args.config else None
+    plan = nv.Plan(rp, ci, A.m, A.k, n, ld=n, dtype=nv.dtype_code(dt), mode=args.mode,
+                   config=cfg, nnz=A.nnz)
     plan_s = time.perf_counter() - t0
     info = plan.info()
     kernel = nv.KERNEL_NAMES[info.config.kernel]
@@ -574,12 +579,15 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": desc, "m": A.m, "k": A.k, "nnz": A.nnz, "n": n,
-                   "kernel": kernel, "mode": args.mode, "shape": info.config.as_dict(),
+                   "kernel": kernel, "mode": "config" if cfg else args.mode,
+                   "shape": info.config.as_dict(),
                    "paper_rule_kernel": "merge" if info.paper_choice else "rowsplit",
                    "plan_build_s": round(plan_s, 3), "input_sha": A.digest()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     "traffic_GBs": (round(traffic / (kavg * 1e-3) / 1e9, 1)
+                                     if traffic is not None else None),
                      "kernel": "k_rowsplit" if kernel == "rowsplit" else "k_merge",
                      "kernel_ms": round(kavg, 4), "algorithmic_bytes": bmin,
                      "gather_model": {"bytes": bgat,
