@@ -557,13 +557,15 @@ def main():
 
     traffic = None
     if os.path.exists(COUNTERS):
-        rec = json.load(open(COUNTERS))
-        key = f"{args.workload}-n{n}-{args.dtype}-{kernel}"
-        r = rec.get(key)
-        if (r and r.get("kernel_source_sha") == kernel_source_hash(r["files"])
-                and r.get("config") in (None, info.config.as_dict())):
-            traffic = round(r["fetch_kib"] * 1024.0 * r["fetch_scale"]
-                            + r["write_kib"] * 1024.0 * r["write_scale"])
+        # one record per launch shape the counters were taken for; only a
+        # record of this exact shape, on the current sources, applies
+        recs = json.load(open(COUNTERS)).get(f"{args.workload}-n{n}-{args.dtype}", [])
+        for r in recs:
+            if (r.get("config") == info.config.as_dict()
+                    and r.get("kernel_source_sha") == kernel_source_hash(r["files"])):
+                traffic = round(r["fetch_kib"] * 1024.0 * r["fetch_scale"]
+                                + r["write_kib"] * 1024.0 * r["write_scale"])
+                break
 
     out = {
         "metric": "SpMM GFLOP/s (2*nnz*n/t)",

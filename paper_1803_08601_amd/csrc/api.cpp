@@ -330,7 +330,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
             q.ws = ws;
         }
         std::vector<float> times;
-        for (int rep = 0; rep < 4; ++rep) {
+        for (int rep = 0; rep < 6; ++rep) {
             TUNE_HIP(hipEventRecord(e0, st));
             rc = forward(q, q.rowptr, q.colind, use_vals, use_B, use_C, st);
             if (rc != SPMM_OK) { cleanup(); return rc; }
