@@ -41,6 +41,21 @@ def kernel_source_hash(files):
     return h.hexdigest()[:16]
 
 
+def counter_traffic(records, key, config):
+    """HBM-side bytes per launch from the rocprofv3 counter records of
+    workload `key`: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the
+    copy calibration. Only a record taken for exactly this launch shape on the
+    current kernel sources applies; otherwise None."""
+    traffic = None
+    for r in records.get(key, []):
+        if (r.get("config") == config
+                and r.get("kernel_source_sha") == kernel_source_hash(r["files"])):
+            traffic = round(r["fetch_kib"] * 1024.0 * r["fetch_scale"]
+                            + r["write_kib"] * 1024.0 * r["write_scale"])
+            break
+    return traffic
+
+
 class HipEvents:
     """Raw hipEvents from the HIP runtime, so that the library can record them
     around its main kernel on the stream it launches on."""
@@ -482,8 +497,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the library and this benchmark use one GPU; --gpus {args.gpus} is not "
+              "supported (multi-GPU sharding is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -509,7 +524,15 @@ def main():
         for _ in range(5):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_dispatch": a.numel() * 4}))
+        t0 = time.perf_counter()
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / 20
+        # a streaming device copy: the practical HBM rate (read + write)
+        print(json.dumps({"copy_bytes_per_dispatch": a.numel() * 4,
+                          "copy_ms": round(t * 1e3, 4),
+                          "copy_read_write_GBs": round(2 * a.numel() * 4 / t / 1e9, 1)}))
         return
 
     dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[args.dtype]
@@ -557,15 +580,8 @@ def main():
 
     traffic = None
     if os.path.exists(COUNTERS):
-        # one record per launch shape the counters were taken for; only a
-        # record of this exact shape, on the current sources, applies
-        recs = json.load(open(COUNTERS)).get(f"{args.workload}-n{n}-{args.dtype}", [])
-        for r in recs:
-            if (r.get("config") == info.config.as_dict()
-                    and r.get("kernel_source_sha") == kernel_source_hash(r["files"])):
-                traffic = round(r["fetch_kib"] * 1024.0 * r["fetch_scale"]
-                                + r["write_kib"] * 1024.0 * r["write_scale"])
-                break
+        traffic = counter_traffic(json.load(open(COUNTERS)), f"{args.workload}-n{n}-{args.dtype}",
+                                  info.config.as_dict())
 
     out = {
         "metric": "SpMM GFLOP/s (2*nnz*n/t)",
