@@ -44,7 +44,7 @@ def stencil():
 
 
 @pytest.mark.parametrize("n", [64, 8])
-@pytest.mark.parametrize("mode", ["autotune", "paper", "merge"])
+@pytest.mark.parametrize("mode", ["autotune", "paper", "merge", "nzsplit"])
 def test_power_law_full(power_law, n, mode):
     A = power_law
     B = wl.dense(1002, A.k, n)
@@ -91,7 +91,7 @@ def test_power_law_integer_exact_full(power_law):
     B = wl.dense(3, A.k, n, kind="int")
     rp, ci = dev(A.rowptr), dev(A.colind)
     ref = oracle.spmm(A.rowptr, A.colind, A.vals, B)
-    for mode in ("merge", "rowsplit"):
+    for mode in ("merge", "rowsplit", "nzsplit"):
         plan = nv.Plan(rp, ci, A.m, A.k, n, mode=mode, nnz=A.nnz)
         C = torch.empty(A.m, n, device="cuda")
         plan.execute(dev(A.vals), dev(B), C)
@@ -168,7 +168,7 @@ def test_batched_full(dtype):
         nv.spmm_batch_destroy(h)
 
 
-@pytest.mark.parametrize("kernel", ["rowsplit", "merge"])
+@pytest.mark.parametrize("kernel", ["rowsplit", "merge", "nzsplit"])
 def test_large_indices(kernel):
     """Row offsets near 2^31 and row * ld beyond 2^31 elements: 64-bit
     address arithmetic in every kernel (and the row-split grid-stride loop).
