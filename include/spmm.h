@@ -141,7 +141,9 @@ typedef struct spmm_batch_s* spmm_batch_t;
  * C = A * B in float32 (Sec. 1). Uses an internal plan cache keyed by
  * (A_rowptr, A_colind, m, k, n, ld, device); on a miss it reads
  * A_rowptr[m] back to the host (one 4-byte copy and a stream sync, so this
- * call is not capture-safe on a miss) and plans in PAPER mode. The structure
+ * call is not capture-safe on a miss) and plans in RULE mode (the Sec. 5.4
+ * procedure re-derived on MI355X; create a plan with SPMM_MODE_PAPER for the
+ * paper's own threshold). The structure
  * behind a cached (A_rowptr, A_colind) pair must not change; call
  * spmm_cache_clear() after changing it. Returns SPMM_OK for m == 0 or n == 0
  * without touching memory. */
@@ -218,7 +220,9 @@ int spmm_plan_destroy(spmm_plan_t plan);
  * spmm_transpose_build: build, once per structure, the CSR of A^T
  * (k rows, m columns): AT_rowptr[k+1], AT_colind[nnz] holding the row ids of
  * A in increasing order within each row of A^T, and perm[nnz] with
- * AT_vals[q] = A_vals[perm[q]]. Stored in the plan; allocates; synchronises. */
+ * AT_vals[q] = A_vals[perm[q]]. Stored in the plan; allocates; synchronises.
+ * The product with A^T gets a plan of its own, made with the plan's mode
+ * (RULE for a plan made from a forced config). */
 int spmm_transpose_build(spmm_plan_t plan, void* stream);
 
 /* Copy the transpose into caller buffers (device pointers: k + 1, nnz, nnz

@@ -645,7 +645,7 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
         if (nnz32 < 0) return fail(SPMM_ERR_INVALID, "A_rowptr[m] < 0");
         if (nnz32 > 0 && (!A_colind || !A_vals || !B))
             return fail(SPMM_ERR_INVALID, "A_colind, A_vals or B is NULL");
-        rc = create_plan(&p, A_rowptr, A_colind, m, k, nnz32, n, ld, SPMM_F32, SPMM_MODE_PAPER,
+        rc = create_plan(&p, A_rowptr, A_colind, m, k, nnz32, n, ld, SPMM_F32, SPMM_MODE_RULE,
                          nullptr, st, false);
         if (rc) return rc;
         std::vector<spmm_plan_s*> evict;

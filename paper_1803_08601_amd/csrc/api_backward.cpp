@@ -60,8 +60,9 @@ int spmm_transpose_build(spmm_plan_t plan, void* stream) {
         free_tr();
         return hip_fail(e, "transpose build");
     }
-    // The product with A^T runs in float32 (values are widened at gather).
-    const int mode = p.mode >= 0 ? p.mode : SPMM_MODE_PAPER;
+    // The product with A^T runs in float32 (values are widened at gather),
+    // planned by the plan's own mode (the MI355X rule for a forced shape).
+    const int mode = p.mode >= 0 ? p.mode : SPMM_MODE_RULE;
     spmm_plan_s* tp = nullptr;
     int rc = create_plan(&tp, tr.at_rowptr, tr.at_colind, p.k, p.m, p.nnz, p.n, p.ld, SPMM_F32,
                          mode, nullptr, st, false);
