@@ -51,6 +51,31 @@ def test_transpose_bit_exact(name):
     assert np.array_equal(perm.cpu().numpy()[:A.nnz], e_perm)
 
 
+@pytest.mark.parametrize("name", ["random_empty", "power_law", "gcn"])
+def test_transpose_twice_is_identity(name):
+    """The transpose of the transpose reproduces A's CSR bit for bit (columns
+    are sorted within rows), and the two value permutations compose to the
+    identity."""
+    A = MATS[name]()
+    plan = make_plan(A, 8)
+    plan.transpose_build()
+    at_rp = torch.empty(A.k + 1, dtype=torch.int32, device="cuda")
+    at_ci = torch.empty(max(A.nnz, 1), dtype=torch.int32, device="cuda")
+    perm = torch.empty(max(A.nnz, 1), dtype=torch.int32, device="cuda")
+    nv.spmm_transpose_get(plan.handle, at_rp, at_ci, perm)
+    plan2 = nv.Plan(at_rp, at_ci, A.k, A.m, 8, nnz=A.nnz, mode="paper")
+    plan2.transpose_build()
+    rp2 = torch.empty(A.m + 1, dtype=torch.int32, device="cuda")
+    ci2 = torch.empty(max(A.nnz, 1), dtype=torch.int32, device="cuda")
+    perm2 = torch.empty(max(A.nnz, 1), dtype=torch.int32, device="cuda")
+    nv.spmm_transpose_get(plan2.handle, rp2, ci2, perm2)
+    torch.cuda.synchronize()
+    assert np.array_equal(rp2.cpu().numpy(), A.rowptr)
+    assert np.array_equal(ci2.cpu().numpy()[:A.nnz], A.colind)
+    p1, p2 = perm.cpu().numpy()[:A.nnz], perm2.cpu().numpy()[:A.nnz]
+    assert np.array_equal(p1[p2], np.arange(A.nnz))
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("name", ["random_empty", "power_law", "dups", "gcn", "wide"])
 @pytest.mark.parametrize("n", [3, 16, 128, 300])

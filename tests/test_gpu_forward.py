@@ -109,20 +109,47 @@ def test_integer_exact(dtype, cfg):
     assert np.array_equal(C.cpu().numpy().astype(np.float64), Cref)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("kernel", [RS, MG, NZ])
-def test_identity_permutation_diagonal_bitwise(kernel):
+def test_identity_permutation_diagonal_bitwise(kernel, dtype):
+    """One product per output element, no additions: A = I gives B, a
+    permutation gives B[pi], a diagonal gives diag * B, bit for bit (the
+    16-bit inputs widen exactly)."""
     k, n = 3000, 32
     rng = np.random.default_rng(0)
-    B = rng.uniform(-1, 1, (k, n)).astype(np.float32)
+    Bt = dev(rng.uniform(-1, 1, (k, n)).astype(np.float32), DT[dtype])
+    B = Bt.float().cpu().numpy()
     I = np.arange(k + 1, dtype=np.int32)
     pi = rng.permutation(k).astype(np.int32)
-    d = rng.uniform(-2, 2, k).astype(np.float32)
-    for cols, vals, expect in [(np.arange(k, dtype=np.int32), np.ones(k, np.float32), B),
-                               (pi, np.ones(k, np.float32), B[pi]),
-                               (np.arange(k, dtype=np.int32), d, d[:, None] * B)]:
-        A = wl.CSR(I, cols, vals, k, k)
-        C, _ = run(A, dev(vals), dev(B), n, config=dict(kernel=kernel))
+    dt = dev(rng.uniform(-2, 2, k).astype(np.float32), DT[dtype])
+    d = dt.float().cpu().numpy()
+    ones = dev(np.ones(k, np.float32), DT[dtype])
+    for cols, vt, expect in [(np.arange(k, dtype=np.int32), ones, B),
+                             (pi, ones, B[pi]),
+                             (np.arange(k, dtype=np.int32), dt, d[:, None] * B)]:
+        A = wl.CSR(I, cols, np.ones(k, np.float32), k, k)
+        C, _ = run(A, vt, Bt, n, config=dict(kernel=kernel))
         assert np.array_equal(C.cpu().numpy(), expect)
+
+
+@pytest.mark.parametrize("kernel", [RS, MG, NZ])
+def test_power_of_two_scaling_and_empty_rows_bitwise(kernel):
+    """(2^e A) B equals 2^e (A B) bit for bit (scaling by a power of two is
+    exact and the plan fixes the summation order), and every empty row is
+    +0.0 in every column."""
+    A = wl.random_csr(31, 4000, 3000, density=0.01, empty_frac=0.4)
+    n = 48
+    B = wl.dense(31, A.k, n)
+    C1, plan = run(A, dev(A.vals), dev(B), n, config=dict(kernel=kernel, items_per_wg=256))
+    for e in (-3, 5):
+        C2 = torch.empty_like(C1)
+        plan.execute(dev(A.vals * np.float32(2.0 ** e)), dev(B), C2)
+        torch.cuda.synchronize()
+        assert torch.equal(C2, C1 * 2.0 ** e)
+    empty = np.nonzero(A.row_lengths() == 0)[0]
+    assert empty.size > 100
+    bits = C1[torch.from_numpy(empty).cuda()].view(torch.int32)
+    assert torch.all(bits == 0)  # +0.0, not -0.0
 
 
 @pytest.mark.parametrize("W", [64, 100, 257, 1024, 4096])

@@ -139,6 +139,25 @@ def test_gcn_bf16_forward_backward_full():
     assert abs(float((dv.double() * vt.double()).sum()) - L) <= 1e-5 * scale
 
 
+def test_gcn_transpose_bit_exact_full():
+    """The GPU radix-sort transpose at full size (16.5M entries, three digit
+    passes, many scan chunks) equals the oracle's counting sort bit for bit."""
+    A = wl.gcn_adjacency(seed=1004)
+    rp, ci = dev(A.rowptr), dev(A.colind)
+    plan = nv.Plan(rp, ci, A.m, A.k, 8, nnz=A.nnz, mode="rule")
+    plan.transpose_build()
+    at_rp = torch.empty(A.k + 1, dtype=torch.int32, device="cuda")
+    at_ci = torch.empty(A.nnz, dtype=torch.int32, device="cuda")
+    perm = torch.empty(A.nnz, dtype=torch.int32, device="cuda")
+    nv.spmm_transpose_get(plan.handle, at_rp, at_ci, perm)
+    torch.cuda.synchronize()
+    e_rp, e_ci, e_perm = oracle.transpose(A.rowptr, A.colind, A.k)
+    assert np.array_equal(at_rp.cpu().numpy(), e_rp)
+    assert np.array_equal(at_ci.cpu().numpy(), e_ci)
+    assert np.array_equal(perm.cpu().numpy(), e_perm)
+    plan.close()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_batched_full(dtype):
     probs = wl.batch_parallel(seed=1005)
