@@ -153,6 +153,7 @@ def gcn_fwd_bwd(steps=20, warmup=3):
         dv = torch.empty(A.nnz, device="cuda")
         fwd = _timed(lambda: plan.execute(vals, Bt, C), steps, warmup)
         bwd_b = _timed(lambda: plan.execute_t(vals, dC, dB), steps, warmup)
+        bwd_s = _timed(lambda: plan.execute_t_scatter(vals, dC, dB), steps, warmup)
         bwd_v = _timed(lambda: plan.sddmm(dC, Bt, dv), steps, warmup)
 
         def step():
@@ -167,7 +168,8 @@ def gcn_fwd_bwd(steps=20, warmup=3):
 
         def gbs(b, ms_):
             return round(b / (ms_ * 1e-3) / 1e9, 1)
-        out[name] = {"fwd_ms": round(fwd, 4), "dB_ms": round(bwd_b, 4), "dvals_ms": round(bwd_v, 4),
+        out[name] = {"fwd_ms": round(fwd, 4), "dB_ms": round(bwd_b, 4),
+                     "dB_scatter_ms": round(bwd_s, 4), "dvals_ms": round(bwd_v, 4),
                      "fwd_bwd_ms": round(total, 4), "transpose_build_ms": round(tr_ms, 2),
                      "fwd_gflops": round(2.0 * A.nnz * n / (fwd * 1e-3) / 1e9, 1),
                      "algorithmic_GBs": {"fwd": gbs(b_fwd, fwd), "dB": gbs(b_db, bwd_b),

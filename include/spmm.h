@@ -236,6 +236,17 @@ int spmm_transpose_get(spmm_plan_t plan, int32_t* AT_rowptr, int32_t* AT_colind,
 int spmm_execute_t(spmm_plan_t plan, const void* A_vals, const float* dC, float* dB,
                    void* stream);
 
+/* The same dB = A^T * dC without a transpose (the SpMM_T of Sec. 6 on the
+ * CSR of A alone): dB is zeroed (columns < n of its k rows), then every
+ * entry p of row i adds A_vals[p] * dC[i, :] into row colind[p] of dB with
+ * float atomic adds, the work split on the merge pieces the plan holds for
+ * SDDMM. Needs no spmm_transpose_build and allocates nothing. The order of
+ * the additions into an element depends on timing, so results are not
+ * bitwise repeatable (they meet the same float32 tolerance; integer-valued
+ * data is exact). dB must not alias dC. Enqueue only. */
+int spmm_execute_t_scatter(spmm_plan_t plan, const void* A_vals, const float* dC, float* dB,
+                           void* stream);
+
 /* dvals[p] = sum_c dC[row(p), c] * B[colind[p], c] for every stored entry
  * p of A (float32 out, nnz entries). dC is float32, B of the plan's dtype.
  * Enqueue only. */

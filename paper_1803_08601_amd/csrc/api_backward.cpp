@@ -107,6 +107,24 @@ int spmm_execute_t(spmm_plan_t plan, const void* A_vals, const float* dC, float*
     return forward(tp, tp.rowptr, tp.colind, plan->tr.at_vals, dC, dB, st);
 }
 
+int spmm_execute_t_scatter(spmm_plan_t plan, const void* A_vals, const float* dC, float* dB,
+                           void* stream) {
+    if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
+    if (plan->k == 0 || plan->n == 0) return SPMM_OK;
+    if (!dB) return fail(SPMM_ERR_INVALID, "dB is NULL");
+    if (plan->nnz > 0 && (!A_vals || !dC)) return fail(SPMM_ERR_INVALID, "A_vals or dC is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool own = plan->cfg.kernel == SPMM_KERNEL_MERGE;
+    const MergeWs& ws = own ? plan->ws : plan->sddmm_ws;
+    const int W = own ? plan->cfg.items_per_wg : kSddmmW;
+    const int64_t P = plan->nnz > 0 && plan->m > 0 ? ws.P : 0;
+    if (P > 0 && !ws.coords) return fail(SPMM_ERR_STATE, "plan has no merge partition");
+    hipError_t e = spmmk::launch_scatter_t(plan->dtype, plan->rowptr, plan->colind, A_vals, dC, dB,
+                                           plan->k, plan->n, plan->ld, ws.coords, P, W, st);
+    if (e != hipSuccess) return hip_fail(e, "scatter launch");
+    return SPMM_OK;
+}
+
 int spmm_sddmm(spmm_plan_t plan, const float* dC, const void* B, float* dvals, void* stream) {
     if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
     if (plan->nnz == 0 || plan->m == 0) return SPMM_OK;

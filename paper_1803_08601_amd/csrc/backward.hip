@@ -405,6 +405,121 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr
     }
 }
 
+// ------------------------------------------------------------------ A^T dC by scatter
+//
+// dB = A^T dC straight from A's CSR, without the transpose: every entry p of
+// row i adds vals[p] * dC[i, :] into row colind[p] of dB with float atomic
+// adds. The work is split on the same diagonal merge pieces as SDDMM (the
+// LDS-staged row ends give each entry's row), so long rows cost no more per
+// entry. A slot covers 4 * 2^g_log2 columns with its lanes interleaved
+// (column base + e * 2^g_log2 + lane), so each atomic instruction of a slot
+// updates consecutive floats of one dB row. The slot keeps the dC chunk of
+// its current row in registers and reloads it when the walk reaches a new
+// row. The order in which additions reach an element depends on timing:
+// results are not bitwise repeatable (integer-valued data is exact).
+constexpr int kScatterVec = 4;
+
+__global__ __launch_bounds__(kBlock) void k_zero_rows(float* __restrict__ a, int64_t rows, int n,
+                                                       int64_t ld) {
+    const int64_t total = rows * n;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x)
+        a[(q / n) * ld + q % n] = 0.f;
+}
+
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_scatter_t(const int* __restrict__ rowptr,
+                                                       const int* __restrict__ colind,
+                                                       const typename S::T* __restrict__ vals,
+                                                       const float* __restrict__ dC,
+                                                       float* __restrict__ dB, int n, int64_t ld,
+                                                       int g_log2, int col_tiles,
+                                                       const int* __restrict__ coords, int W) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* s_val = reinterpret_cast<float*>(smem);       // [W]
+    int* s_col = reinterpret_cast<int*>(s_val + W);      // [W]
+    int* s_rowend = s_col + W;                           // [W] local row ends
+    const int tile = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int i0 = coords[2 * tile], j0 = coords[2 * tile + 1];
+    const int i1 = coords[2 * tile + 2], j1 = coords[2 * tile + 3];
+    const int nr = i1 - i0, nj = j1 - j0;
+    for (int t = threadIdx.x; t < nr; t += kBlock)
+        s_rowend[t] = __builtin_nontemporal_load(rowptr + i0 + 1 + t) - j0;
+    for (int t = threadIdx.x; t < nj; t += kBlock) {
+        s_col[t] = __builtin_nontemporal_load(colind + j0 + t);
+        s_val[t] = load_elem(vals + j0 + t, S{});
+    }
+    __syncthreads();
+
+    const int G = 1 << g_log2;
+    const int NS = kBlock >> g_log2;
+    const int slot = threadIdx.x >> g_log2;
+    const int g = threadIdx.x & (G - 1);
+    const int items = nr + nj;
+    const int ips = (items + NS - 1) / NS;
+    const int d0 = min(slot * ips, items), d1 = min(d0 + ips, items);
+    auto search = [&](int d) {
+        int lo = max(0, d - nj), hi = min(d, nr);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_rowend[mid] + mid < d) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    const int rs = search(d0);
+    const int js = d0 - rs;
+    const int je = d1 - search(d1);
+    const int span = kScatterVec << g_log2;
+    for (int t = 0; t < col_tiles; ++t) {
+        const int base = t * span + g;
+        int r = rs, have = -1;
+        float d[kScatterVec];
+        for (int j = js; j < je; ++j) {
+            while (r < nr && s_rowend[r] <= j) ++r;  // rows that end before entry j
+            if (r != have) {
+#pragma unroll
+                for (int e = 0; e < kScatterVec; ++e) {
+                    const int col = base + e * G;
+                    d[e] = col < n ? dC[(int64_t)(i0 + r) * ld + col] : 0.f;
+                }
+                have = r;
+            }
+            const float v = s_val[j];
+            float* dst = dB + (int64_t)s_col[j] * ld;
+#pragma unroll
+            for (int e = 0; e < kScatterVec; ++e) {
+                const int col = base + e * G;
+                if (col < n) unsafeAtomicAdd(dst + col, v * d[e]);
+            }
+        }
+    }
+}
+
+hipError_t launch_scatter_t(int dtype, const int* rowptr, const int* colind, const void* vals,
+                            const float* dC, float* dB, int64_t k, int64_t n, int64_t ld,
+                            const int* coords, int64_t P, int W, hipStream_t st) {
+    if (k <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_rows, dim3(grid_for(k * n)), dim3(kBlock), 0, st, dB, k, (int)n, ld);
+    if (P <= 0) return hipGetLastError();
+    int g_log2 = 0;
+    while (g_log2 < 6 && (int64_t(kScatterVec) << g_log2) < n) ++g_log2;
+    const int span = kScatterVec << g_log2;
+    const int col_tiles = (int)((n + span - 1) / span);
+    const size_t lds = sizeof(int) * 3 * (size_t)W;
+#define SCATTER_LAUNCH(SS, T)                                                                  \
+    hipLaunchKernelGGL((k_scatter_t<SS>), dim3((uint32_t)P), dim3(kBlock), lds, st, rowptr,     \
+                       colind, static_cast<const T*>(vals), dC, dB, (int)n, ld, g_log2,        \
+                       col_tiles, coords, W)
+    switch (dtype) {
+    case 0: SCATTER_LAUNCH(F32, float); break;
+    case 1: SCATTER_LAUNCH(BF16, uint16_t); break;
+    case 2: SCATTER_LAUNCH(F16, uint16_t); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SCATTER_LAUNCH
+    return hipGetLastError();
+}
+
 template <class S, int VEC>
 static hipError_t sddmm_go(int unroll, int g_log2, int col_tiles, const int* rowptr,
                            const int* colind, const float* dC, const void* B, float* dvals,

@@ -76,6 +76,12 @@ hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int
 
 // dvals[p] = <dC[row(p), :n], B[colind[p], :n]> over the P merge pieces of W
 // items given by coords (2 * (P + 1) ints).
+// dB = A^T dC by float atomic adds on diagonal merge pieces (dB is zeroed
+// first); not bitwise repeatable.
+hipError_t launch_scatter_t(int dtype, const int* rowptr, const int* colind, const void* vals,
+                            const float* dC, float* dB, int64_t k, int64_t n, int64_t ld,
+                            const int* coords, int64_t P, int W, hipStream_t st);
+
 hipError_t launch_sddmm(int dtype, int vec, int unroll, int g_log2, int col_tiles,
                         const int* rowptr, const int* colind, const float* dC, const void* B,
                         float* dvals, int64_t n, int64_t ld, const int* coords, int64_t P, int W,

@@ -77,6 +77,7 @@ _SIGS = {
     "spmm_transpose_build": [_VP, _VP],
     "spmm_transpose_get": [_VP, _VP, _VP, _VP, _VP],
     "spmm_execute_t": [_VP, _VP, _VP, _VP, _VP],
+    "spmm_execute_t_scatter": [_VP, _VP, _VP, _VP, _VP],
     "spmm_sddmm": [_VP, _VP, _VP, _VP, _VP],
     "spmm_batch_plan": [_VP, _VP, _I64, _I32, _I32, _VP],
     "spmm_batch_run": [_VP, _VP],
@@ -223,6 +224,12 @@ def spmm_execute_t(plan, A_vals, dC, dB, stream=None):
                                                          _stream(stream)))
 
 
+def spmm_execute_t_scatter(plan, A_vals, dC, dB, stream=None):
+    return _check("spmm_execute_t_scatter",
+                  lib().spmm_execute_t_scatter(plan, _ptr(A_vals), _ptr(dC), _ptr(dB),
+                                               _stream(stream)))
+
+
 def spmm_sddmm(plan, dC, B, dvals, stream=None):
     return _check("spmm_sddmm", lib().spmm_sddmm(plan, _ptr(dC), _ptr(B), _ptr(dvals),
                                                  _stream(stream)))
@@ -298,6 +305,10 @@ class Plan:
 
     def execute_t(self, vals, dC, dB, stream=None):
         spmm_execute_t(self.handle, vals, dC, dB, stream)
+        return dB
+
+    def execute_t_scatter(self, vals, dC, dB, stream=None):
+        spmm_execute_t_scatter(self.handle, vals, dC, dB, stream)
         return dB
 
     def sddmm(self, dC, B, dvals, stream=None):

@@ -97,6 +97,11 @@ def test_grad_b_and_vals_vs_oracle(dtype, name, n):
     ref_dB = oracle.spmm_t(A.rowptr, A.colind, v, dC, A.k, vals_tag=vtag)
     N_dB = oracle.spmm_t(A.rowptr, A.colind, v, dC, A.k, vals_tag=vtag, absval=True)
     assert rel_err(dB.cpu().numpy(), ref_dB, N_dB) <= TOL_F32
+    # the transpose-free scatter form of the same product
+    dBs = torch.full((A.k, n), float("nan"), device="cuda")
+    plan.execute_t_scatter(vt, dCt, dBs)
+    torch.cuda.synchronize()
+    assert rel_err(dBs.cpu().numpy(), ref_dB, N_dB) <= TOL_F32
     ref_dv = oracle.sddmm(A.rowptr, A.colind, dC, b, b_tag=btag)
     N_dv = oracle.sddmm(A.rowptr, A.colind, dC, b, b_tag=btag, absval=True)
     assert rel_err(dv.cpu().numpy()[:A.nnz], ref_dv, N_dv) <= TOL_F32
@@ -104,6 +109,29 @@ def test_grad_b_and_vals_vs_oracle(dtype, name, n):
         r32 = oracle.sddmm(A.rowptr, A.colind, dC, B)
         n32 = oracle.sddmm(A.rowptr, A.colind, dC, B, absval=True)
         assert rel_err(dv.cpu().numpy()[:A.nnz], r32, n32) <= TOL_STORAGE_16
+
+
+@pytest.mark.parametrize("kernel", [RS, MG, NZ])
+@pytest.mark.parametrize("n", [5, 32, 300])
+def test_scatter_transpose_free(kernel, n):
+    """dB = A^T dC by atomic scatter on A's CSR, without spmm_transpose_build:
+    integer data exact whatever the order of the additions; padding columns
+    of dB untouched; repeated calls overwrite (dB is zeroed by the call)."""
+    A = wl.power_law(seed=19, m=12_000, cap=6_000, values="int")
+    dC = wl.dense(20, A.m, n, kind="int")
+    ld = n + 3
+    dCp = np.zeros((A.m, ld), np.float32)
+    dCp[:, :n] = dC
+    plan = nv.Plan(dev(A.rowptr), dev(A.colind), A.m, A.k, n, ld=ld, nnz=A.nnz,
+                   config=dict(kernel=kernel))
+    assert not plan.info().has_transpose
+    dB = torch.full((A.k, ld), 7.0, device="cuda")
+    ref = oracle.spmm_t(A.rowptr, A.colind, A.vals, dC, A.k)
+    for _ in range(2):
+        plan.execute_t_scatter(dev(A.vals), dev(dCp), dB)
+        torch.cuda.synchronize()
+        assert np.array_equal(dB[:, :n].cpu().numpy(), ref)
+    assert torch.all(dB[:, n:] == 7.0)
 
 
 @pytest.mark.parametrize("kernel,mode", [(RS, "paper"), (MG, "paper"), (NZ, "paper"),
