@@ -410,6 +410,36 @@ def nz_compare(n=64):
         torch.cuda.empty_cache()
 
 
+def table_size_sweep(n=64):
+    """Where the gather time comes from: the same 16M power-law entries
+    (1M rows, mean 16) against B tables of 1M, 500k, 250k, 64k and 16k rows
+    (256 MB down to 4 MB at n = 64), each merge-walk kernel at W = 2048,
+    U = 2. A table that fits one XCD's 4 MB L2 shows the on-chip gather rate;
+    the larger ones show whether the 256 MB MALL changes it."""
+    import torch
+    from paper_1803_08601_amd import native as nv
+    from paper_1803_08601_amd import workloads as wl
+    rng = np.random.default_rng(5)
+    M = 1_000_000
+    lengths, _ = wl.power_law_lengths(rng, M, mean=16.0, cap=16_000)
+    rp = torch.from_numpy(wl.rowptr_from_lengths(lengths)).cuda()
+    nnz = int(lengths.sum())
+    C = torch.empty(M, n, device="cuda")
+    for k in (1_000_000, 500_000, 250_000, 64_000, 16_000):
+        ci = torch.from_numpy(wl.distinct_sorted_columns(rng, lengths, k)).cuda()
+        vals = torch.rand(nnz, device="cuda")
+        B = torch.rand(k, n, device="cuda")
+        rec = {"k": k, "B_MB": round(k * n * 4 / 1e6, 1), "nnz": nnz, "n": n}
+        for name, code in (("merge_ms", nv.SPMM_KERNEL_MERGE), ("nzsplit_ms", nv.SPMM_KERNEL_NZSPLIT)):
+            ms, _ = _plan_time(nv, rp, ci, M, k, nnz, n, vals, B, C,
+                               cfg=dict(kernel=code, items_per_wg=2048, unroll=2), steps=20)
+            rec[name] = round(ms, 4)
+        rec["gather_TBs"] = round(nnz * n * 4 / (min(rec["merge_ms"], rec["nzsplit_ms"]) * 1e-3) / 1e12, 2)
+        print(json.dumps(rec), flush=True)
+        del ci, vals, B
+        torch.cuda.empty_cache()
+
+
 def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1)):
     """Sparse versus dense (Fig. 7): a 100k x 100k matrix with a fixed share
     of distinct random columns in every row times a 100k x 64 B, SpMM (plan by
@@ -492,6 +522,8 @@ def main():
     ap.add_argument("--nzsplit", action="store_true",
                     help="nonzero split against merge path and row split on matrices with "
                          "runs of empty rows")
+    ap.add_argument("--table-size-sweep", action="store_true",
+                    help="the same entries against B tables from 256 MB down to 4 MB")
     ap.add_argument("--crossover", action="store_true",
                     help="sparse versus dense product over density (100k x 100k, n = 64)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -519,6 +551,9 @@ def main():
         return
     if args.nzsplit:
         nz_compare(args.n)
+        return
+    if args.table_size_sweep:
+        table_size_sweep(args.n)
         return
     if args.copy_calibration:
         a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
