@@ -75,6 +75,9 @@ spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec) {
     s.unroll = p.cfg.unroll;
     s.W = p.cfg.items_per_wg;
     s.nz = p.cfg.kernel == SPMM_KERNEL_NZSPLIT ? 1 : 0;
+    const int64_t row_bytes = p.ld * elem_bytes(p.dtype);
+    s.short_addr = p.k < (int64_t(1) << 24) && row_bytes < (int64_t(1) << 24) &&
+                   p.k * row_bytes <= int64_t(0xffffffff);
     return s;
 }
 

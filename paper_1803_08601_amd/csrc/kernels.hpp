@@ -21,6 +21,7 @@ struct Shape {
     int W = 1024;       // merge items per workgroup (nonzeros for the nonzero split)
     int col_tiles = 1;
     int nz = 0;         // merge walk over nonzero-split pieces (1-D partition)
+    int short_addr = 0; // B has < 2^24 rows of < 2^24 bytes and spans < 4 GiB
 };
 
 // Operands of one forward product; coords, P and the carry arrays are the

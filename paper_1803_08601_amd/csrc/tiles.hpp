@@ -72,7 +72,7 @@ struct MaxTimes {
 
 // One workgroup's rows of the row-split product (rows blk * R .. blk * R + R - 1
 // with R = rows per workgroup) for column tile `coltile`.
-template <class S, int VEC, int U, class R = PlusTimes>
+template <class S, int VEC, int U, class R = PlusTimes, bool SHORT = false>
 __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
                                                const int* __restrict__ colind,
                                                const typename S::T* __restrict__ vals,
@@ -118,47 +118,82 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
         }
     };
     if (p0 < p1) load_pair(p0, cc0, cv0, cc1, cv1);
+    const int TS = 1 << ts_log2;
+    const int G = 1 << g_log2;
+    // Byte address of this lane's first pair in the team (ds_bpermute takes
+    // a byte lane address); step k of a chunk reads entry (k << ts_log2) +
+    // slot, held by lane team_base + that entry (first pair member, k < G) or
+    // that entry - TL (second member).
+    const int my4 = (team_base + slot) << 2;
+    auto b_row = [&](int c) -> const typename S::T* {
+        if constexpr (SHORT) {
+            // B spans < 4 GiB and < 2^24 rows of < 2^24 bytes: a 24-bit
+            // multiply and a 32-bit offset from B's base in scalar registers
+            const uint32_t off = __umul24((uint32_t)c, (uint32_t)(ld * sizeof(typename S::T))) +
+                                 (uint32_t)(col * sizeof(typename S::T));
+            return reinterpret_cast<const typename S::T*>(reinterpret_cast<const char*>(B) + off);
+        } else {
+            return B + (int64_t)c * ld + col;
+        }
+    };
     for (int base = p0; base < p1; base += CH) {
         const int cnt = min(CH, p1 - base);
         const bool more = base + CH < p1;  // uniform within the team
         int nc0 = 0, nc1 = 0;
         float nv0 = 0.f, nv1 = 0.f;
         if (more) load_pair(base + CH, nc0, nv0, nc1, nv1);
-        const int nsteps = (cnt + (1 << ts_log2) - 1) >> ts_log2;
-        for (int s = 0; s < nsteps; s += U) {
-            int c[U];
-            float v[U];
-            bool ok[U];
+        const int nsteps = (cnt + TS - 1) >> ts_log2;       // the same for the team
+        const int nvalid = (cnt - slot + TS - 1) >> ts_log2;  // steps holding this slot's entries
+        // Steps [kbeg, kend) read pair member (creg, vreg); sub4 shifts the
+        // second member's entries back to lanes 0 .. TL - 1.
+        auto run = [&](int kbeg, int kend, int creg, float vreg, int sub4) {
+            const int lim = min(kend, nvalid);
+            for (int k = kbeg; k < kend; k += U) {
+                int c[U];
+                float v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                // entry index within the chunk; steps below G read the first
-                // pair member, the rest the second (the same for every slot)
-                const int idx = ((s + u) << ts_log2) + slot;
-                const bool second = ((s + u) >> g_log2) != 0;
-                ok[u] = idx < cnt;
-                const int src = team_base + (idx & (TL - 1));
-                c[u] = __shfl(second ? cc1 : cc0, src, kWave);
-                const float vv = __shfl(second ? cv1 : cv0, src, kWave);
-                v[u] = ok[u] ? vv : 0.f;
-            }
-            float b[U][VEC];
+                for (int u = 0; u < U; ++u) {
+                    // every lane of the team takes part in both permutes
+                    const int addr = my4 + (((k + u) << ts_log2) << 2) - sub4;
+                    c[u] = __builtin_amdgcn_ds_bpermute(addr, creg);
+                    v[u] = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(vreg)));
+                }
+                if (col_ok && k + U <= lim) {
+                    // a whole block of this slot's entries: no per-entry checks
+                    float b[U][VEC];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (ok[u] && col_ok) {
-                    load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
+                    for (int u = 0; u < U; ++u) load_row<S, VEC>(b_row(c[u]), b[u]);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
+                    }
                 } else {
+                    bool ok[U];
+                    float b[U][VEC];
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
+                    for (int u = 0; u < U; ++u) {
+                        ok[u] = k + u < lim;
+                        if (!ok[u]) v[u] = 0.f;
+                        if (ok[u] && col_ok) {
+                            load_row<S, VEC>(b_row(c[u]), b[u]);
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (R::kZeroTermIsNeutral || ok[u]) {
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
+                        }
+                    }
                 }
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (R::kZeroTermIsNeutral || ok[u]) {
-#pragma unroll
-                    for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
-                }
-            }
-        }
+        };
+        run(0, min(G, nsteps), cc0, cv0, 0);
+        if (nsteps > G) run(G, nsteps, cc1, cv1, TL << 2);
         cc0 = nc0; cc1 = nc1; cv0 = nv0; cv1 = nv1;
     }
     // Combine the team's slots (lanes G, 2G, ... apart) by a butterfly.
@@ -447,7 +482,7 @@ __device__ __forceinline__ void merge_fixup_piece(float* __restrict__ C, int64_t
 
 // ---------------------------------------------------------------- kernels
 
-template <class S, int VEC, int U, class R>
+template <class S, int VEC, int U, class R, bool SHORT>
 __global__ __launch_bounds__(kBlock) void k_rowsplit(const int* __restrict__ rowptr,
                                                       const int* __restrict__ colind,
                                                       const typename S::T* __restrict__ vals,
@@ -457,8 +492,8 @@ __global__ __launch_bounds__(kBlock) void k_rowsplit(const int* __restrict__ row
     const int rpb_log2 = (6 - g_log2 - ts_log2) + 2;
     const int64_t nblk = (m + (int64_t(1) << rpb_log2) - 1) >> rpb_log2;
     for (int64_t blk = xcd_remap(blockIdx.x, gridDim.x); blk < nblk; blk += gridDim.x)
-        rowsplit_block<S, VEC, U, R>(rowptr, colind, vals, B, C, m, n, ld, g_log2, ts_log2, blk,
-                                     blockIdx.y);
+        rowsplit_block<S, VEC, U, R, SHORT>(rowptr, colind, vals, B, C, m, n, ld, g_log2,
+                                            ts_log2, blk, blockIdx.y);
 }
 
 template <class S, int VEC, int U, class R, bool NZ>
@@ -496,9 +531,14 @@ hipError_t launch_one(bool merge, const Shape& s, const ForwardArgs& a, hipStrea
         const int64_t rows_per_block = int64_t(kWave >> tl_log2) * (kBlock / kWave);
         const int64_t need = (a.m + rows_per_block - 1) / rows_per_block;
         const uint32_t grid = (uint32_t)(need < (1 << 22) ? need : (1 << 22));
-        hipLaunchKernelGGL((k_rowsplit<S, VEC, U, R>), dim3(grid, s.col_tiles), dim3(kBlock), 0,
-                           st, a.rowptr, a.colind, vals, B, a.C, a.m, (int)a.n, a.ld, s.g_log2,
-                           s.ts_log2);
+        if (s.short_addr)
+            hipLaunchKernelGGL((k_rowsplit<S, VEC, U, R, true>), dim3(grid, s.col_tiles),
+                               dim3(kBlock), 0, st, a.rowptr, a.colind, vals, B, a.C, a.m,
+                               (int)a.n, a.ld, s.g_log2, s.ts_log2);
+        else
+            hipLaunchKernelGGL((k_rowsplit<S, VEC, U, R, false>), dim3(grid, s.col_tiles),
+                               dim3(kBlock), 0, st, a.rowptr, a.colind, vals, B, a.C, a.m,
+                               (int)a.n, a.ld, s.g_log2, s.ts_log2);
     } else {
         const dim3 grid((uint32_t)a.P, s.col_tiles);
         if (s.nz)

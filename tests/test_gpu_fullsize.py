@@ -188,6 +188,30 @@ def test_batched_full(dtype):
 
 
 @pytest.mark.parametrize("kernel", ["rowsplit", "merge", "nzsplit"])
+def test_more_than_2_24_rows_of_b(kernel):
+    """k above 2^24: the row split leaves its 24-bit row-offset multiply for
+    64-bit addressing (B rows near the end of a 268 MB B are gathered)."""
+    m, k, n = 3000, (1 << 24) + 100, 4
+    rng = np.random.default_rng(77)
+    per = 9
+    rp = np.arange(0, (m + 1) * per, per, dtype=np.int32)
+    ci = np.sort(rng.integers(k - 5000, k, (m, per)), axis=1).reshape(-1).astype(np.int32)
+    vals = rng.integers(-8, 9, m * per).astype(np.float32)
+    A = wl.CSR(rp, ci, vals, m, k)
+    Bt = torch.randint(-8, 9, (k, n), device="cuda", dtype=torch.int32).float()
+    plan = nv.Plan(dev(rp), dev(ci), m, k, n, mode=kernel, nnz=A.nnz)
+    C = torch.empty(m, n, device="cuda")
+    plan.execute(dev(vals), Bt, C)
+    torch.cuda.synchronize()
+    rows_used = np.unique(ci)
+    sub = Bt[torch.from_numpy(rows_used.astype(np.int64)).cuda()].cpu().numpy()
+    remap = np.searchsorted(rows_used, ci).astype(np.int32)
+    ref = oracle.spmm(rp, remap, vals, sub)
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), ref)
+    plan.close()
+
+
+@pytest.mark.parametrize("kernel", ["rowsplit", "merge", "nzsplit"])
 def test_large_indices(kernel):
     """Row offsets near 2^31 and row * ld beyond 2^31 elements: 64-bit
     address arithmetic in every kernel (and the row-split grid-stride loop).
