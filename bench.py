@@ -181,6 +181,56 @@ def gcn_fwd_bwd(steps=20, warmup=3):
     return out
 
 
+def other_configs(A_pl, steps=20, warmup=3):
+    """The remaining single-product workloads, each planned by timing: the
+    power-law matrix at n = 8, the same at n = 64 with BF16 storage, and the
+    27-point stencil on 128^3 at n = 16 and n = 128 (float32). Main-kernel
+    time from hipEvents, as for the headline."""
+    import torch
+    from paper_1803_08601_amd import native as nv
+    from paper_1803_08601_amd import workloads as wl
+    ev = HipEvents()
+    out = {}
+
+    def one(label, A, n, dt, seed):
+        rp, ci = torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colind).cuda()
+        vals = torch.from_numpy(A.vals).to(dt).cuda()
+        Bt = torch.from_numpy(wl.dense(seed, A.k, n)).to(dt).cuda()
+        C = torch.empty(A.m, n, device="cuda")
+        plan = nv.Plan(rp, ci, A.m, A.k, n, dtype=nv.dtype_code(dt), mode="autotune", nnz=A.nnz)
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            plan.execute(vals, Bt, C)
+        e0 = [ev.create() for _ in range(steps)]
+        e1 = [ev.create() for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            nv.spmm_execute_events(plan.handle, vals, Bt, C, e0[i], e1[i], stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        kms = float(np.mean([ev.elapsed_ms(e0[i], e1[i]) for i in range(steps)]))
+        for e in e0 + e1:
+            ev.destroy(e)
+        sz = torch.tensor([], dtype=dt).element_size()
+        bmin = bytes_min(A.m, A.k, A.nnz, n, sz, sz)
+        out[label] = {"n": n, "dtype": str(dt).replace("torch.", ""), "nnz": A.nnz,
+                      "kernel": nv.KERNEL_NAMES[plan.info().config.kernel],
+                      "ms_per_step": round(ms, 4), "kernel_ms": round(kms, 4),
+                      "gflops": round(2.0 * A.nnz * n / (ms * 1e-3) / 1e9, 1),
+                      "roofline_frac": round(bmin / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        plan.close()
+        del rp, ci, vals, Bt, C
+        torch.cuda.empty_cache()
+
+    one("powerlaw_n8_f32", A_pl, 8, torch.float32, 1002)
+    one("powerlaw_n64_bf16", A_pl, 64, torch.bfloat16, 1002)
+    S = wl.stencil27(seed=1003)
+    one("stencil_n16_f32", S, 16, torch.float32, 1003)
+    one("stencil_n128_f32", S, 128, torch.float32, 1003)
+    return out
+
+
 def batched(steps=10, warmup=2):
     """512 uneven products (m = k log-uniform in [1e3, 2e5], half U{8..64}
     rows and half Zipf-2.1 rows, n from {8, 32, 128}) in one persistent
@@ -515,7 +565,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true",
                     help="only the headline product (skip the GCN fwd+bwd and batched extras)")
-    ap.add_argument("--only-extra", choices=["gcn", "batch"],
+    ap.add_argument("--only-extra", choices=["gcn", "batch", "configs"],
                     help="run just one extra measurement and print its JSON (for profiling)")
     ap.add_argument("--sweep", action="store_true",
                     help="kernel-choice sweep over mean row length (re-derives the Sec. 5.4 threshold)")
@@ -543,7 +593,13 @@ def main():
         heuristic_sweep(args.n)
         return
     if args.only_extra:
-        rec = gcn_fwd_bwd(args.steps, args.warmup) if args.only_extra == "gcn" else batched(args.steps, args.warmup)
+        if args.only_extra == "configs":
+            from paper_1803_08601_amd import workloads as wl
+            rec = other_configs(wl.power_law(seed=1002), args.steps, args.warmup)
+        elif args.only_extra == "gcn":
+            rec = gcn_fwd_bwd(args.steps, args.warmup)
+        else:
+            rec = batched(args.steps, args.warmup)
         print(json.dumps(rec), flush=True)
         return
     if args.crossover:
@@ -655,7 +711,8 @@ def main():
         del C, Bt, vals
         plan.close()
         torch.cuda.empty_cache()
-        out["extra"] = {"gcn_fwd_bwd": gcn_fwd_bwd(), "batched": batched()}
+        out["extra"] = {"other_configs": other_configs(A) if args.workload == "powerlaw" else {},
+                        "gcn_fwd_bwd": gcn_fwd_bwd(), "batched": batched()}
     print(json.dumps(out), flush=True)
 
 
