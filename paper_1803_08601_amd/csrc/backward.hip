@@ -315,15 +315,15 @@ hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int
 // (the Phase 1 partition of Algorithm 1), so that the work per workgroup is
 // the same whatever the row lengths: a 159k-entry row costs no more per entry
 // than a short one. A workgroup stages its piece's row ends and column indices
-// in LDS; its slots (2^g_log2 lanes covering one column tile of a row) split
-// the piece evenly with the diagonal search on the LDS copy and walk their
-// entries in order, finding each entry's row among the staged row ends. For U
-// entries at a time a slot gathers the B row chunks and the dC row chunks
-// (the latter mostly cache hits, as neighbouring entries share rows), forms
-// the partial dot products over all column tiles, and sums its lanes with DPP
-// row exchanges; lane 0 writes dvals. No entry depends on another, so there is
-// no carry-out.
-template <class S, int VEC, int U>
+// in LDS; its wavefronts split the piece evenly with the diagonal search on
+// the LDS copy, and the slots of a wavefront (2^g_log2 lanes covering one
+// column tile of a row) take its entries interleaved, finding each entry's
+// row among the staged row ends. For U entries at a time a slot gathers the
+// B row chunks, forms the partial dot products with the dC row chunk (kept
+// in registers while the row lasts when the row fits one column tile), and
+// sums its lanes with DPP row exchanges; lane 0 writes dvals. No entry
+// depends on another, so there is no carry-out.
+template <class S, int VEC, int U, bool ONE_TILE>
 __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr,
                                                    const int* __restrict__ colind,
                                                    const float* __restrict__ dC,
@@ -344,12 +344,17 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr
     __syncthreads();
 
     const int G = 1 << g_log2;
-    const int NS = kBlock >> g_log2;
-    const int slot = threadIdx.x >> g_log2;
     const int g = threadIdx.x & (G - 1);
+    // The piece is split among the workgroup's wavefronts by the diagonal
+    // search; inside a wavefront its SPW slots take interleaved entries (slot
+    // s: entries s, s + SPW, ...), so they walk the same rows together.
+    const int NW = kBlock / kWave;
+    const int w = threadIdx.x / kWave;
+    const int SPW = kWave >> g_log2;
+    const int s = (threadIdx.x & (kWave - 1)) >> g_log2;
     const int items = nr + nj;
-    const int ips = (items + NS - 1) / NS;
-    const int d0 = min(slot * ips, items), d1 = min(d0 + ips, items);
+    const int ipw = (items + NW - 1) / NW;
+    const int d0 = min(w * ipw, items), d1 = min(d0 + ipw, items);
     auto search = [&](int d) {
         int lo = max(0, d - nj), hi = min(d, nr);
         while (lo < hi) {
@@ -362,12 +367,18 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr
     const int js = d0 - r;
     const int je = d1 - search(d1);
     const int span = VEC << g_log2;
-    for (int jb = js; jb < je; jb += U) {
+    // With one column tile the dC chunk of the current row stays in
+    // registers and is reloaded when the walk reaches a new row; the slots of
+    // a wavefront reach row ends together, so that branch is nearly uniform.
+    int have = -1;
+    float dh[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) dh[e] = 0.f;
+    for (int jb = js + s; jb < je; jb += SPW * U) {
         int rr[U], c[U];
-        float part[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int j = jb + u;
+            const int j = jb + u * SPW;
             if (j < je) {
                 while (r < nr && s_rowend[r] <= j) ++r;  // rows that end before entry j
                 c[u] = s_col[j];
@@ -375,32 +386,61 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr
                 c[u] = 0;
             }
             rr[u] = r;
-            part[u] = 0.f;
         }
-        for (int t = 0; t < col_tiles; ++t) {
-            const int col = t * span + g * VEC;
+        float part[U];
+        if constexpr (ONE_TILE) {
+            const int col = g * VEC;
             const bool col_ok = col < n;
-            float b[U][VEC], d[U][VEC];
+            float b[U][VEC];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (jb + u < je && col_ok) {
+                if (jb + u * SPW < je && col_ok) {
                     load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
-                    load_f32<VEC>(dC + (int64_t)(i0 + rr[u]) * ld + col, d[u]);
                 } else {
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) b[u][e] = d[u][e] = 0.f;
+                    for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                if (rr[u] != have) {
+                    if (col_ok && jb + u * SPW < je)
+                        load_f32<VEC>(dC + (int64_t)(i0 + rr[u]) * ld + col, dh);
+                    have = rr[u];
+                }
+                part[u] = 0.f;
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) part[u] = fmaf(d[u][e], b[u][e], part[u]);
+                for (int e = 0; e < VEC; ++e) part[u] = fmaf(dh[e], b[u][e], part[u]);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) part[u] = 0.f;
+            for (int t = 0; t < col_tiles; ++t) {
+                const int col = t * span + g * VEC;
+                const bool col_ok = col < n;
+                float b[U][VEC], d[U][VEC];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (jb + u * SPW < je && col_ok) {
+                        load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
+                        load_f32<VEC>(dC + (int64_t)(i0 + rr[u]) * ld + col, d[u]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) b[u][e] = d[u][e] = 0.f;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) part[u] = fmaf(d[u][e], b[u][e], part[u]);
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             part[u] = group_sum(part[u], g_log2);
-            if (g == 0 && jb + u < je) __builtin_nontemporal_store(part[u], dvals + j0 + jb + u);
+            if (g == 0 && jb + u * SPW < je)
+                __builtin_nontemporal_store(part[u], dvals + j0 + jb + u * SPW);
         }
     }
 }
@@ -528,8 +568,14 @@ static hipError_t sddmm_go(int unroll, int g_log2, int col_tiles, const int* row
     const size_t lds = sizeof(int) * 2 * (size_t)W;
     const typename S::T* Bp = static_cast<const typename S::T*>(B);
 #define SDDMM_LAUNCH(UU)                                                                         \
-    hipLaunchKernelGGL((k_sddmm<S, VEC, UU>), dim3((uint32_t)P), dim3(kBlock), lds, st, rowptr, \
-                       colind, dC, Bp, dvals, (int)n, ld, g_log2, col_tiles, coords, W)
+    if (col_tiles == 1)                                                                          \
+        hipLaunchKernelGGL((k_sddmm<S, VEC, UU, true>), dim3((uint32_t)P), dim3(kBlock), lds,   \
+                           st, rowptr, colind, dC, Bp, dvals, (int)n, ld, g_log2, col_tiles,    \
+                           coords, W);                                                           \
+    else                                                                                         \
+        hipLaunchKernelGGL((k_sddmm<S, VEC, UU, false>), dim3((uint32_t)P), dim3(kBlock), lds,  \
+                           st, rowptr, colind, dC, Bp, dvals, (int)n, ld, g_log2, col_tiles,    \
+                           coords, W)
     switch (unroll) {
     case 1: SDDMM_LAUNCH(1); break;
     case 2: SDDMM_LAUNCH(2); break;
