@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <string>
@@ -500,8 +501,11 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
 
 // ------------------------------------------------------------------ plan cache
 
+// Cached plans are shared: a call holds its own reference while it enqueues
+// work, so an eviction by another thread frees the plan only after that.
 using CacheKey = std::tuple<const void*, const void*, int64_t, int64_t, int64_t, int64_t, int>;
-static std::map<CacheKey, spmm_plan_s*> g_cache;
+using PlanRef = std::shared_ptr<spmm_plan_s>;
+static std::map<CacheKey, PlanRef> g_cache;
 static std::vector<CacheKey> g_cache_order;  // least recently used first
 static constexpr size_t kCacheCap = 64;
 
@@ -631,7 +635,7 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
     int dev = 0;
     SPMM_HIP(hipGetDevice(&dev));
     const CacheKey key{A_rowptr, A_colind, m, k, n, ld, dev};
-    spmm_plan_s* p = nullptr;
+    PlanRef p;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_cache.find(key);
@@ -649,21 +653,28 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
         if (nnz32 < 0) return fail(SPMM_ERR_INVALID, "A_rowptr[m] < 0");
         if (nnz32 > 0 && (!A_colind || !A_vals || !B))
             return fail(SPMM_ERR_INVALID, "A_colind, A_vals or B is NULL");
-        rc = create_plan(&p, A_rowptr, A_colind, m, k, nnz32, n, ld, SPMM_F32, SPMM_MODE_RULE,
+        spmm_plan_s* fresh = nullptr;
+        rc = create_plan(&fresh, A_rowptr, A_colind, m, k, nnz32, n, ld, SPMM_F32, SPMM_MODE_RULE,
                          nullptr, st, false);
         if (rc) return rc;
-        std::vector<spmm_plan_s*> evict;
+        p = PlanRef(fresh, destroy_plan);
+        std::vector<PlanRef> evict;  // released after the lock
         {
             std::lock_guard<std::mutex> lk(g_mu);
-            g_cache[key] = p;
-            g_cache_order.push_back(key);
+            auto it = g_cache.find(key);
+            if (it != g_cache.end()) {
+                evict.push_back(p);  // another thread cached this key meanwhile: use its plan
+                p = it->second;
+            } else {
+                g_cache[key] = p;
+                g_cache_order.push_back(key);
+            }
             while (g_cache_order.size() > kCacheCap) {
                 evict.push_back(g_cache[g_cache_order.front()]);
                 g_cache.erase(g_cache_order.front());
                 g_cache_order.erase(g_cache_order.begin());
             }
         }
-        for (auto* q : evict) destroy_plan(q);
     } else if (p->nnz > 0 && (!A_colind || !A_vals || !B)) {
         return fail(SPMM_ERR_INVALID, "A_colind, A_vals or B is NULL");
     }
@@ -671,14 +682,13 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
 }
 
 int spmm_cache_clear(void) {
-    std::vector<spmm_plan_s*> all;
+    std::vector<PlanRef> all;  // plans in use elsewhere are freed by their last user
     {
         std::lock_guard<std::mutex> lk(g_mu);
         for (auto& kv : g_cache) all.push_back(kv.second);
         g_cache.clear();
         g_cache_order.clear();
     }
-    for (auto* p : all) destroy_plan(p);
     return SPMM_OK;
 }
 

@@ -288,6 +288,52 @@ def test_spmm_csr_one_call_and_cache():
         nv.spmm_csr(rp, ci, v, Bt, C, A.m, A.k, n, n - 1)
 
 
+def test_streams_and_threads():
+    """Plans run on two streams at once and the one-call entry point used from
+    two host threads give the same results as serial runs (plan workspaces
+    are per plan; the plan cache and registry are locked)."""
+    import threading
+    mats = [wl.power_law(seed=61, m=30_000, cap=10_000), wl.stencil27(g=24)]
+    n = 32
+    data = []
+    for A in mats:
+        B = wl.dense(62, A.k, n)
+        rp, ci, v, Bt = dev(A.rowptr), dev(A.colind), dev(A.vals), dev(B)
+        data.append((A, rp, ci, v, Bt))
+    ref = []
+    for A, rp, ci, v, Bt in data:
+        C = torch.empty(A.m, n, device="cuda")
+        nv.Plan(rp, ci, A.m, A.k, n, nnz=A.nnz, mode="rule").execute(v, Bt, C)
+        torch.cuda.synchronize()
+        ref.append(C)
+    plans = [nv.Plan(rp, ci, A.m, A.k, n, nnz=A.nnz, mode="rule") for A, rp, ci, v, Bt in data]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.empty(A.m, n, device="cuda") for A, *_ in data]
+    for rep in range(3):
+        for (A, rp, ci, v, Bt), plan, st, C in zip(data, plans, streams, outs):
+            with torch.cuda.stream(st):
+                plan.execute(v, Bt, C, stream=st.cuda_stream)
+        torch.cuda.synchronize()
+        for C, R in zip(outs, ref):
+            assert torch.equal(C, R)
+    nv.spmm_cache_clear()
+    res = [None, None]
+    def work(i):
+        A, rp, ci, v, Bt = data[i]
+        C = torch.empty(A.m, n, device="cuda")
+        for _ in range(3):
+            nv.spmm_csr(rp, ci, v, Bt, C, A.m, A.k, n, n)
+        torch.cuda.synchronize()
+        res[i] = C
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for C, R in zip(res, ref):
+        assert torch.equal(C, R)
+
+
 def test_validate():
     A = wl.random_csr(6, 100, 80, density=0.1)
     rp, ci = dev(A.rowptr), dev(A.colind)
