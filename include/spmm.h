@@ -272,15 +272,20 @@ typedef struct spmm_problem {
 int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, int64_t count,
                     int32_t dtype, int32_t mode, void* stream);
 
-/* Launch the captured graph on `stream`: all products of the batch. */
+/* Launch the captured graph on `stream`: all products of the batch. The
+ * batch's work queues live in the batch object, so runs of one batch must
+ * not overlap (queue them on one stream, or wait between streams); runs of
+ * different batches may. Enqueue only. */
 int spmm_batch_run(spmm_batch_t batch, void* stream);
 
-/* The same work without the graph: direct kernel launches on `stream`. */
+/* The same work without the graph: direct kernel launches on `stream`
+ * (same rule on overlapping runs). */
 int spmm_batch_run_direct(spmm_batch_t batch, void* stream);
 
 /* Per-problem chosen config (problem index b). */
 int spmm_batch_problem_config(spmm_batch_t batch, int64_t b, spmm_config* config_host);
 
+/* Free the batch, its plans and its graph (synchronises the device first). */
 int spmm_batch_destroy(spmm_batch_t batch);
 
 /* ---------------------------------------------------------------- misc */
