@@ -139,7 +139,8 @@ typedef struct spmm_batch_s* spmm_batch_t;
 
 /* ---------------------------------------------------------------- one call
  * C = A * B in float32 (Sec. 1). Uses an internal plan cache keyed by
- * (A_rowptr, A_colind, m, k, n, ld, device); on a miss it reads
+ * (A_rowptr, A_colind, m, k, n, ld, device, stream), safe to call from
+ * several host threads; on a miss it reads
  * A_rowptr[m] back to the host (one 4-byte copy and a stream sync, so this
  * call is not capture-safe on a miss) and plans in RULE mode (the Sec. 5.4
  * procedure re-derived on MI355X; create a plan with SPMM_MODE_PAPER for the
@@ -176,7 +177,10 @@ int spmm_plan_create_config(spmm_plan_t* out_plan, const int32_t* A_rowptr,
 
 /* C = A * B with the plan's kernel: row split (Sec. 4.1) or merge-based
  * Phases 2-3 of Algorithm 1 (Sec. 4.2). A_vals and B are of the plan's
- * dtype; C is float32. Enqueue only. */
+ * dtype; C is float32. Enqueue only. The carry-out workspace of a
+ * merge-based plan belongs to the plan: products (and SDDMM or A^T calls)
+ * with one plan must not overlap on different streams; use one plan per
+ * stream. */
 int spmm_execute(spmm_plan_t plan, const void* A_vals, const void* B, float* C, void* stream);
 
 /* The same as spmm_execute, for measurement: records the caller's events

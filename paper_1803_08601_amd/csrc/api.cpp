@@ -503,7 +503,8 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
 
 // Cached plans are shared: a call holds its own reference while it enqueues
 // work, so an eviction by another thread frees the plan only after that.
-using CacheKey = std::tuple<const void*, const void*, int64_t, int64_t, int64_t, int64_t, int>;
+using CacheKey =
+    std::tuple<const void*, const void*, int64_t, int64_t, int64_t, int64_t, int, const void*>;
 using PlanRef = std::shared_ptr<spmm_plan_s>;
 static std::map<CacheKey, PlanRef> g_cache;
 static std::vector<CacheKey> g_cache_order;  // least recently used first
@@ -634,7 +635,9 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
     hipStream_t st = static_cast<hipStream_t>(stream);
     int dev = 0;
     SPMM_HIP(hipGetDevice(&dev));
-    const CacheKey key{A_rowptr, A_colind, m, k, n, ld, dev};
+    // keyed by stream too: a merge-based plan's carry-out workspace must not be
+    // shared by work on two streams
+    const CacheKey key{A_rowptr, A_colind, m, k, n, ld, dev, stream};
     PlanRef p;
     {
         std::lock_guard<std::mutex> lk(g_mu);
