@@ -334,6 +334,33 @@ def test_streams_and_threads():
         assert torch.equal(C, R)
 
 
+def test_shape_limits_and_degenerate_plans():
+    """The largest merge pieces (8192 items: 108 KB of LDS in FP32, 116 KB
+    with 16-bit storage, within gfx950's 160 KB per workgroup) give the right
+    product; larger ones are refused with SPMM_ERR_UNSUPPORTED before any
+    launch; plans with no rows, one column or no entries work for every
+    kernel."""
+    A = wl.power_law(seed=71, m=6000, cap=3000)
+    n = 64
+    B = wl.dense(71, A.k, n)
+    for dt in ("f32", "bf16"):
+        for kern in (MG, NZ):
+            vt, Bt = dev(A.vals, DT[dt]), dev(B, DT[dt])
+            C, _ = run(A, vt, Bt, n, config=dict(kernel=kern, items_per_wg=8192))
+            check(A, vt, Bt, n, C)
+    with pytest.raises(nv.SpmmError) as ei:
+        run(A, dev(A.vals), dev(B), n, config=dict(kernel=MG, items_per_wg=16384))
+    assert ei.value.status == nv.SPMM_ERR_UNSUPPORTED
+    for kern in (RS, MG, NZ):
+        empty = wl.CSR(np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32), 0, 10)
+        Ce = torch.empty(0, 8, device="cuda")
+        run(empty, dev(np.zeros(1, np.float32)), dev(wl.dense(1, 10, 8)), 8, config=dict(kernel=kern),
+            C=Ce)
+        one_col = wl.random_csr(72, 500, 1, density=0.7)
+        C1, _ = run(one_col, dev(one_col.vals), dev(wl.dense(2, 1, 1)), 1, config=dict(kernel=kern))
+        check(one_col, dev(one_col.vals), dev(wl.dense(2, 1, 1)), 1, C1)
+
+
 def test_validate():
     A = wl.random_csr(6, 100, 80, density=0.1)
     rp, ci = dev(A.rowptr), dev(A.colind)
