@@ -183,9 +183,11 @@ def gcn_fwd_bwd(steps=20, warmup=3):
 
 def other_configs(A_pl, steps=20, warmup=3):
     """The remaining single-product workloads, each planned by timing: the
-    power-law matrix at n = 8, the same at n = 64 with BF16 storage, and the
-    27-point stencil on 128^3 at n = 16 and n = 128 (float32). Main-kernel
-    time from hipEvents, as for the headline."""
+    uniform 4096 x 4096 matrix with 16 entries per row at n = 32 (a
+    launch-bound size), the power-law matrix at n = 8, the same at n = 64
+    with BF16 storage, and the 27-point stencil on 128^3 at n = 16 and
+    n = 128 (float32). Main-kernel time from hipEvents, as for the
+    headline."""
     import torch
     from paper_1803_08601_amd import native as nv
     from paper_1803_08601_amd import workloads as wl
@@ -223,6 +225,7 @@ def other_configs(A_pl, steps=20, warmup=3):
         del rp, ci, vals, Bt, C
         torch.cuda.empty_cache()
 
+    one("plain_4096_n32_f32", wl.plain(seed=1001), 32, torch.float32, 1001)
     one("powerlaw_n8_f32", A_pl, 8, torch.float32, 1002)
     one("powerlaw_n64_bf16", A_pl, 64, torch.bfloat16, 1002)
     S = wl.stencil27(seed=1003)
