@@ -22,13 +22,12 @@ int spmm_transpose_build(spmm_plan_t plan, void* stream) {
     hipStream_t st = static_cast<hipStream_t>(stream);
     spmm_plan_s& p = *plan;
     Transpose& tr = p.tr;
-    int *k0 = nullptr, *k1 = nullptr, *v1 = nullptr, *r0 = nullptr, *hist = nullptr;
+    // The sort's temporaries (two key arrays, values, row ids, histogram and scan
+    // scratch) share one allocation: one hipMalloc and one hipFree instead of five.
+    int *tmp = nullptr, *k0 = nullptr, *k1 = nullptr, *v1 = nullptr, *r0 = nullptr,
+        *hist = nullptr;
     auto free_tmp = [&]() {
-        if (k0) (void)hipFree(k0);
-        if (k1) (void)hipFree(k1);
-        if (v1) (void)hipFree(v1);
-        if (r0) (void)hipFree(r0);
-        if (hist) (void)hipFree(hist);
+        if (tmp) (void)hipFree(tmp);
     };
     auto free_tr = [&]() {
         if (tr.at_rowptr) (void)hipFree(tr.at_rowptr);
@@ -41,12 +40,18 @@ int spmm_transpose_build(spmm_plan_t plan, void* stream) {
     if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&tr.at_colind, sizeof(int) * p.nnz);
     if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&tr.perm, sizeof(int) * p.nnz);
     if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&tr.at_vals, sizeof(float) * p.nnz);
-    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&k0, sizeof(int) * p.nnz);
-    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&k1, sizeof(int) * p.nnz);
-    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&v1, sizeof(int) * p.nnz);
-    if (e == hipSuccess && p.nnz > 0) e = hipMalloc(&r0, sizeof(int) * p.nnz);
-    if (e == hipSuccess && p.nnz > 0)
-        e = hipMalloc(&hist, sizeof(int) * spmmk::transpose_scratch_len(p.nnz));
+    if (e == hipSuccess && p.nnz > 0) {
+        const size_t arr = ((size_t)p.nnz + 63) / 64 * 64;  // 256-byte aligned pieces
+        const size_t total = 4 * arr + (size_t)spmmk::transpose_scratch_len(p.nnz);
+        e = hipMalloc(&tmp, sizeof(int) * total);
+        if (e == hipSuccess) {
+            k0 = tmp;
+            k1 = tmp + arr;
+            v1 = tmp + 2 * arr;
+            r0 = tmp + 3 * arr;
+            hist = tmp + 4 * arr;
+        }
+    }
     if (e == hipSuccess) {
         if (p.nnz > 0)
             e = spmmk::transpose_build(p.rowptr, p.colind, p.m, p.k, p.nnz, tr.at_rowptr,

@@ -87,16 +87,31 @@ __global__ __launch_bounds__(kBlock) void k_row_stats(const int* __restrict__ ro
         nlong += __shfl_xor(nlong, off, kWave);
         bad |= __shfl_xor(bad, off, kWave);
     }
+    // One set of atomics per workgroup: atomics from every wave on the same three
+    // words serialise in L2 and cost more than the whole scan of rowptr.
+    __shared__ int part[3][kBlock / kWave];
+    const int wave = threadIdx.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == 0) {
+        part[0][wave] = mx;
+        part[1][wave] = nlong;
+        part[2][wave] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; ++w) {
+            mx = max(mx, part[0][w]);
+            nlong += part[1][w];
+            bad |= part[2][w];
+        }
         atomicMax(&stats[0], mx);
-        atomicAdd(&stats[1], nlong);
+        if (nlong) atomicAdd(&stats[1], nlong);
         if (bad) atomicAnd(&stats[2], 0);
     }
 }
 
 hipError_t launch_row_stats(const int* rowptr, int64_t m, int* stats, hipStream_t st) {
     int64_t blocks = (m + kBlock - 1) / kBlock;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 256) blocks = 256;  // one workgroup per CU: few same-word atomics
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_row_stats, dim3((uint32_t)blocks), dim3(kBlock), 0, st, rowptr, m, stats);
     return hipGetLastError();
