@@ -13,27 +13,39 @@
 
 namespace spmmk {
 
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
-constexpr int kSortRounds = 32;                    // 64-item rounds per tile
-constexpr int kSortTile = kWave * kSortRounds;     // items per tile (one wavefront per tile)
+constexpr int kRadixMaxBits = 8;                   // digits of at most 8 bits per pass
+constexpr int kRadix = 1 << kRadixMaxBits;
+constexpr int kSortWaves = kBlock / kWave;         // wavefronts per tile
+constexpr int kSortRounds = 8;                     // 64-item rounds per wavefront
+constexpr int kSortTile = kBlock * kSortRounds;    // items per tile (one workgroup per tile)
 
-// Per-tile digit counts: hist[d * ntiles + t].
-__global__ __launch_bounds__(kWave) void k_radix_hist(const int* __restrict__ keys, int64_t n,
-                                                       int shift, int64_t ntiles,
-                                                       int* __restrict__ hist) {
+// Index within the tile of round r of a lane: wavefront w owns the
+// contiguous quarter [w * 512, (w + 1) * 512) of the tile.
+__device__ __forceinline__ int sort_item(int w, int r, int lane) {
+    return (w * kSortRounds + r) * kWave + lane;
+}
+
+// Per-tile digit counts: hist[d * ntiles + t] for the 2^bits digits.
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const int* __restrict__ keys, int64_t n,
+                                                        int shift, int bits, int64_t ntiles,
+                                                        int* __restrict__ hist) {
     __shared__ int cnt[kRadix];
     const int64_t t = blockIdx.x;
-    for (int d = threadIdx.x; d < kRadix; d += kWave) cnt[d] = 0;
+    const int radix = 1 << bits;
+    if (threadIdx.x < radix) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = t * kSortTile;
-#pragma unroll 8
+    int key[kSortRounds];  // all loads in flight before the first count
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        const int64_t i = base + r * kWave + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadix - 1)], 1);
+        const int64_t i = base + r * kBlock + threadIdx.x;
+        key[r] = i < n ? keys[i] : -1;
     }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r)
+        if (key[r] >= 0) atomicAdd(&cnt[(key[r] >> shift) & (radix - 1)], 1);
     __syncthreads();
-    for (int d = threadIdx.x; d < kRadix; d += kWave) hist[(int64_t)d * ntiles + t] = cnt[d];
+    if (threadIdx.x < radix) hist[(int64_t)threadIdx.x * ntiles + t] = cnt[threadIdx.x];
 }
 
 // Device-wide exclusive scan of int32 in place, in three launches: per-chunk
@@ -138,57 +150,99 @@ static hipError_t exclusive_scan(int* a, int64_t len, int* sums, hipStream_t st)
 }
 
 // Stable scatter of one digit pass, carrying two value arrays (entry
-// position and row of A). One wavefront walks its tile in rounds of 64
-// consecutive items, with the whole tile's keys and values loaded up front;
-// within a round, lanes holding the same digit find each other with 8
-// ballots and take ranks in lane order, so item order is kept within the
-// tile; tiles are placed in order by the scanned counts.
-__global__ __launch_bounds__(kWave) void k_radix_scatter(const int* __restrict__ keys_in,
-                                                          const int* __restrict__ vals_in,
-                                                          const int* __restrict__ rows_in,
-                                                          int* __restrict__ keys_out,
-                                                          int* __restrict__ vals_out,
-                                                          int* __restrict__ rows_out, int64_t n,
-                                                          int shift, int64_t ntiles,
-                                                          const int* __restrict__ offs) {
-    __shared__ int next[kRadix];
+// position and row of A). One workgroup per tile; each wavefront loads its
+// quarter of the tile into registers and counts its digits in LDS. The
+// counts give every (wavefront, digit) pair its first slot in the tile sorted
+// by digit; a wavefront then ranks its items round by round (lanes with equal
+// digits find each other with one ballot per digit bit and take ranks in lane
+// order), which sorts the tile in LDS stably. The sorted tile is written out
+// in order: consecutive slots of one digit go to consecutive global
+// positions, so the stores of a digit's run coalesce instead of each item
+// being a separate store to a random place.
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const int* __restrict__ keys_in,
+                                                           const int* __restrict__ vals_in,
+                                                           const int* __restrict__ rows_in,
+                                                           int* __restrict__ keys_out,
+                                                           int* __restrict__ vals_out,
+                                                           int* __restrict__ rows_out, int64_t n,
+                                                           int shift, int bits, int64_t ntiles,
+                                                           const int* __restrict__ offs) {
+    __shared__ int s_key[kSortTile], s_val[kSortTile], s_row[kSortTile];
+    __shared__ int cursor[kSortWaves][kRadix];  // next slot of (wavefront, digit)
+    __shared__ int delta[kRadix];  // global position of a digit's slot minus the slot
+    __shared__ int s_wave[kSortWaves];
     const int64_t t = blockIdx.x;
-    const int lane = threadIdx.x;
-    for (int d = lane; d < kRadix; d += kWave) next[d] = offs[(int64_t)d * ntiles + t];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int radix = 1 << bits, mask = radix - 1;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = t * kSortTile;
+    const int tile_n = (int)(n - base < kSortTile ? n - base : kSortTile);
     int key[kSortRounds], val[kSortRounds], row[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        const int64_t i = base + r * kWave + lane;
-        const bool ok = i < n;
-        key[r] = ok ? keys_in[i] : 0;
-        val[r] = ok ? vals_in[i] : 0;
-        row[r] = ok ? rows_in[i] : 0;
+        const int j = sort_item(w, r, lane);
+        const bool ok = j < tile_n;
+        key[r] = ok ? keys_in[base + j] : 0;
+        val[r] = ok ? vals_in[base + j] : 0;
+        row[r] = ok ? rows_in[base + j] : 0;
+    }
+    for (int d = lane; d < radix; d += kWave) cursor[w][d] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r)
+        if (sort_item(w, r, lane) < tile_n) atomicAdd(&cursor[w][(key[r] >> shift) & mask], 1);
+    __syncthreads();
+    {
+        // thread d owns digit d: the tile's count, its exclusive scan over the
+        // digits, then the first slot of each wavefront's run of that digit
+        const int d = threadIdx.x;
+        int c[kSortWaves];
+        int total_d = 0;
+#pragma unroll
+        for (int q = 0; q < kSortWaves; ++q) {
+            c[q] = d < radix ? cursor[q][d] : 0;
+            total_d += c[q];
+        }
+        int all;
+        const int start = block_exclusive_scan(total_d, s_wave, &all);
+        __syncthreads();
+        if (d < radix) {
+            int run = start;
+#pragma unroll
+            for (int q = 0; q < kSortWaves; ++q) {
+                cursor[q][d] = run;
+                run += c[q];
+            }
+            delta[d] = offs[(int64_t)d * ntiles + t] - start;
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-        const int64_t i = base + r * kWave + lane;
-        const bool ok = i < n;
-        const int d = (key[r] >> shift) & (kRadix - 1);
+        const bool ok = sort_item(w, r, lane) < tile_n;
+        const int d = (key[r] >> shift) & mask;
         uint64_t match = __ballot(ok);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
+        for (int b = 0; b < bits; ++b) {
             const uint64_t ones = __ballot(ok && ((d >> b) & 1));
             match &= ((d >> b) & 1) ? ones : ~ones;
         }
-        const int rank = __popcll(match & lt);
-        const int pos = ok ? next[d] + rank : 0;
+        const int slot = ok ? cursor[w][d] + __popcll(match & lt) : 0;
         __syncthreads();
         if (ok) {
-            keys_out[pos] = key[r];
-            vals_out[pos] = val[r];
-            rows_out[pos] = row[r];
+            s_key[slot] = key[r];
+            s_val[slot] = val[r];
+            s_row[slot] = row[r];
             // the highest lane of each digit group advances that digit's cursor
-            if ((match >> lane) == 1ull) next[d] = pos + 1;
+            if ((match >> lane) == 1ull) cursor[w][d] = slot + 1;
         }
         __syncthreads();
+    }
+    for (int j = threadIdx.x; j < tile_n; j += kBlock) {
+        const int kk = s_key[j];
+        const int pos = delta[(kk >> shift) & mask] + j;
+        keys_out[pos] = kk;
+        vals_out[pos] = s_val[j];
+        rows_out[pos] = s_row[j];
     }
 }
 
@@ -257,21 +311,25 @@ hipError_t transpose_build(const int* rowptr, const int* colind, int64_t m, int6
                        tmp_rows0);
     int bits = 0;
     while (bits < 31 && (int64_t(1) << bits) < k) ++bits;
-    const int passes = (bits + kRadixBits - 1) / kRadixBits;
+    // as few passes as digits of at most 8 bits allow, the bits spread evenly:
+    // narrower digits mean longer runs per digit in a tile, so fewer stores
+    const int passes = (bits + kRadixMaxBits - 1) / kRadixMaxBits;
     const int64_t ntiles = (nnz + kSortTile - 1) / kSortTile;
-    const int64_t hlen = ntiles * kRadix;
     int* hist = scratch;
-    int* sums = scratch + hlen;
+    int* sums = scratch + ntiles * kRadix;
     int *kin = tmp_keys0, *kout = tmp_keys1, *vin = perm, *vout = tmp_vals1;
     int *rin = tmp_rows0, *rout = at_colind;
+    int shift = 0;
     for (int ps = 0; ps < passes; ++ps) {
-        const int shift = ps * kRadixBits;
-        hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)ntiles), dim3(kWave), 0, st, kin, nnz,
-                           shift, ntiles, hist);
+        const int pbits = (bits - shift + (passes - ps) - 1) / (passes - ps);
+        const int64_t hlen = ntiles << pbits;
+        hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)ntiles), dim3(kBlock), 0, st, kin, nnz,
+                           shift, pbits, ntiles, hist);
         e = exclusive_scan(hist, hlen, sums, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)ntiles), dim3(kWave), 0, st, kin, vin,
-                           rin, kout, vout, rout, nnz, shift, ntiles, hist);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)ntiles), dim3(kBlock), 0, st, kin, vin,
+                           rin, kout, vout, rout, nnz, shift, pbits, ntiles, hist);
+        shift += pbits;
         int* tk = kin; kin = kout; kout = tk;
         int* tv = vin; vin = vout; vout = tv;
         int* tr = rin; rin = rout; rout = tr;
