@@ -268,8 +268,42 @@ def spmm_csr_validate(A_rowptr, A_colind, m, k, nnz, stream=None):
 
 # ---------------------------------------------------------------- plan wrapper
 
+def _dtype_of(code):
+    import torch
+    return {SPMM_F32: torch.float32, SPMM_BF16: torch.bfloat16, SPMM_F16: torch.float16}[code]
+
+
+def _require(t, name, dtype, rows, ld, n):
+    """Refuse a tensor the kernels would read or write outside of, or read
+    with another layout: it must be on the GPU, of the given dtype, and hold
+    `rows` rows of stride `ld` of which the first `n` entries are used (a 1-D
+    operand is one row). Accepted layouts: contiguous memory of at least
+    (rows - 1) * ld + n elements, read as rows of stride `ld`, or a 2-D view
+    with strides (ld, 1) of at least `rows` x `n`."""
+    if rows <= 0 or n <= 0:
+        return
+    if t is None:
+        raise ValueError(f"{name} is None")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, the plan needs {dtype}")
+    need = (rows - 1) * ld + n
+    if t.is_contiguous():
+        if t.numel() < need:
+            raise ValueError(f"{name} has {t.numel()} elements; {rows} rows of stride {ld} "
+                             f"with {n} used need {need}")
+        return
+    if not (t.dim() == 2 and t.stride(1) == 1 and t.stride(0) == ld):
+        raise ValueError(f"{name}: rows of stride {ld} needed, got strides {t.stride()}")
+    if t.shape[0] < rows or t.shape[1] < n:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}; {rows} rows of {n} needed")
+
+
 class Plan:
-    """Owns a plan handle for one CSR structure (tensors kept alive here)."""
+    """Owns a plan handle for one CSR structure (tensors kept alive here).
+    Its methods check each tensor's device, dtype and extent against the plan
+    before the call (the C entry points take raw pointers)."""
 
     def __init__(self, rowptr, colind, m, k, n, ld=None, dtype=SPMM_F32, mode="paper",
                  config=None, nnz=None, stream=None):
@@ -278,6 +312,9 @@ class Plan:
         self.ld = int(n if ld is None else ld)
         self.nnz = int(colind.numel() if nnz is None else nnz)
         self.dtype = dtype
+        import torch
+        _require(rowptr, "rowptr", torch.int32, 1, self.m + 1, self.m + 1 if self.m > 0 else 0)
+        _require(colind, "colind", torch.int32, 1, self.nnz, self.nnz)
         if config is not None:
             cfg = config if isinstance(config, spmm_config) else spmm_config(**config)
             self.handle = spmm_plan_create_config(rowptr, colind, self.m, self.k, self.nnz, self.n,
@@ -289,11 +326,21 @@ class Plan:
     def info(self):
         return spmm_plan_info_get(self.handle)
 
+    def _check_forward(self, vals, B, C):
+        import torch
+        dt = _dtype_of(self.dtype)
+        if self.m > 0 and self.n > 0:
+            _require(vals, "vals", dt, 1, self.nnz, self.nnz)
+            _require(B, "B", dt, self.k, self.ld, self.n)
+        _require(C, "C", torch.float32, self.m, self.ld, self.n)
+
     def execute(self, vals, B, C, stream=None):
+        self._check_forward(vals, B, C)
         spmm_execute(self.handle, vals, B, C, stream)
         return C
 
     def execute_semiring(self, semiring, vals, B, C, stream=None):
+        self._check_forward(vals, B, C)
         spmm_execute_semiring(self.handle, semiring, vals, B, C, stream)
         return C
 
@@ -303,15 +350,29 @@ class Plan:
     def transpose_build(self, stream=None):
         spmm_transpose_build(self.handle, stream)
 
+    def _check_transposed(self, vals, dC, dB):
+        import torch
+        if self.k > 0 and self.n > 0:
+            _require(vals, "vals", _dtype_of(self.dtype), 1, self.nnz, self.nnz)
+            _require(dC, "dC", torch.float32, self.m, self.ld, self.n)
+        _require(dB, "dB", torch.float32, self.k, self.ld, self.n)
+
     def execute_t(self, vals, dC, dB, stream=None):
+        self._check_transposed(vals, dC, dB)
         spmm_execute_t(self.handle, vals, dC, dB, stream)
         return dB
 
     def execute_t_scatter(self, vals, dC, dB, stream=None):
+        self._check_transposed(vals, dC, dB)
         spmm_execute_t_scatter(self.handle, vals, dC, dB, stream)
         return dB
 
     def sddmm(self, dC, B, dvals, stream=None):
+        import torch
+        if self.m > 0 and self.nnz > 0:
+            _require(dvals, "dvals", torch.float32, 1, self.nnz, self.nnz)
+            _require(dC, "dC", torch.float32, self.m, self.ld, self.n)
+            _require(B, "B", _dtype_of(self.dtype), self.k, self.ld, self.n)
         spmm_sddmm(self.handle, dC, B, dvals, stream)
         return dvals
 

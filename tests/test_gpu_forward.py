@@ -373,6 +373,43 @@ def test_validate():
         nv.spmm_csr_validate(dev(bad), ci, A.m, A.k, A.nnz)
 
 
+def test_plan_methods_refuse_bad_tensors():
+    """The Python plan checks dtype, device and extent before any launch: a
+    tensor too short for rows of stride ld, a wrong dtype, a host tensor or a
+    view with other strides raises ValueError and leaves C untouched."""
+    A = wl.random_csr(7, 120, 90, density=0.1)
+    n, ld = 6, 10
+    plan = nv.Plan(dev(A.rowptr), dev(A.colind), A.m, A.k, n, ld=ld, nnz=A.nnz)
+    vals, B = dev(A.vals), torch.ones(A.k, ld, device="cuda")
+    C = torch.full((A.m, ld), 3.0, device="cuda")
+    bad = [
+        (vals[:-1], B, C),                                   # vals shorter than nnz
+        (vals.to(torch.bfloat16), B, C),                     # dtype of another plan
+        (vals, torch.ones(A.k, n, device="cuda"), C),        # B rows of stride n < ld
+        (vals, B.to(torch.float16), C),
+        (vals, B, torch.empty(A.m, n, device="cuda")),       # C too short for stride ld
+        (vals, B, C.to(torch.float64)),
+        (vals.cpu(), B, C),                                  # host memory
+        (vals, B.t().contiguous().t(), C),                   # column-major view
+    ]
+    for v, b_, c in bad:
+        with pytest.raises(ValueError):
+            plan.execute(v, b_, c)
+    dv = torch.empty(A.nnz, device="cuda")
+    with pytest.raises(ValueError):
+        plan.sddmm(torch.empty(A.m, n, device="cuda"), B, dv)
+    with pytest.raises(ValueError):
+        plan.sddmm(torch.empty(A.m, ld, device="cuda"), B, dv[:-1])
+    torch.cuda.synchronize()
+    assert torch.all(C == 3.0)
+    # accepted: contiguous memory read as rows of stride ld, and (ld, 1) views
+    plan.execute(vals, B.reshape(-1), C)
+    plan.execute(vals, B, torch.empty(A.m, 2 * ld, device="cuda")[:, :ld].contiguous())
+    big = torch.full((A.m, ld + 4), 5.0, device="cuda")
+    with pytest.raises(ValueError):
+        plan.execute(vals, B, big[:, :ld])                   # stride ld + 4, not ld
+
+
 def test_rule_mode_choice():
     """The MI355X rule: merge-based for power-law rows (a row of >= 4096
     entries) or a mean below 4, row split for regular rows."""
