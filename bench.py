@@ -583,10 +583,28 @@ def cpu_baseline(A, B, n, budget_s=10.0, max_reps=8):
         oracle.spmm(A.rowptr, A.colind, A.vals, B, n=n, nthreads=threads)
         times.append(time.perf_counter() - t0)
     t = float(np.median(times))
+    # one thread on a bounded sample: the first rows holding about an eighth
+    # of the entries (results are identical for any thread count)
+    rows = int(np.searchsorted(A.rowptr, A.nnz // 8))
+    t0 = time.perf_counter()
+    oracle.spmm_rows(A.rowptr, A.colind, A.vals, B, np.arange(rows, dtype=np.int64), n=n,
+                     nthreads=1)
+    t1 = time.perf_counter() - t0
+    nnz1 = int(A.rowptr[rows])
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": 2.0 * A.nnz * n / t / 1e9, "unit": "GFLOP/s", "cores": threads,
             "kind": "oracle",
             "sample": f"full workload, {len(times)} passes of the FP64 oracle (OpenMP over rows, "
-                      f"{threads} threads), median {t * 1e3:.1f} ms per pass"}
+                      f"{threads} threads), median {t * 1e3:.1f} ms per pass",
+            "one_thread": {"value": round(2.0 * nnz1 * n / t1 / 1e9, 3), "unit": "GFLOP/s",
+                           "sample": f"first {rows} rows ({nnz1} entries), one pass"},
+            "cpu_model": model}
 
 
 def main():
