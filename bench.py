@@ -48,8 +48,12 @@ def counter_traffic(records, key, config):
     current kernel sources applies; otherwise None."""
     traffic = None
     for r in records.get(key, []):
-        if (r.get("config") == config
-                and r.get("kernel_source_sha") == kernel_source_hash(r["files"])):
+        rc = r.get("config", {})
+        # a shape field missing from the record (added to the config later)
+        # held its default, 0, when the counters were taken
+        same = (all(config.get(k) == v for k, v in rc.items())
+                and all(v == 0 for k, v in config.items() if k not in rc))
+        if same and r.get("kernel_source_sha") == kernel_source_hash(r["files"]):
             traffic = round(r["fetch_kib"] * 1024.0 * r["fetch_scale"]
                             + r["write_kib"] * 1024.0 * r["write_scale"])
             break
@@ -616,7 +620,8 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--mode", default="autotune",
-                    choices=["autotune", "paper", "rowsplit", "merge", "nzsplit", "rule"])
+                    choices=["autotune", "paper", "rowsplit", "merge", "nzsplit", "rule",
+                             "rowblock"])
     ap.add_argument("--config", default=None,
                     help="force a kernel shape, JSON of spmm_config fields, e.g. "
                          "'{\"kernel\": 1, \"items_per_wg\": 2048, \"unroll\": 2}'")
@@ -761,7 +766,8 @@ def main():
                      "traffic": traffic,
                      "traffic_GBs": (round(traffic / (kavg * 1e-3) / 1e9, 1)
                                      if traffic is not None else None),
-                     "kernel": "k_rowsplit" if kernel == "rowsplit" else "k_merge",
+                     "kernel": {"rowsplit": "k_rowsplit", "rowblock": "k_rowblock"}.get(kernel,
+                                                                                        "k_merge"),
                      "kernel_ms": round(kavg, 4), "algorithmic_bytes": bmin,
                      "gather_model": {"bytes": bgat,
                                       "achieved": round(bgat / (kavg * 1e-3) / 1e9, 1),

@@ -73,14 +73,21 @@ typedef enum spmm_dtype { SPMM_F32 = 0, SPMM_BF16 = 1, SPMM_F16 = 2 } spmm_dtype
  *              several workgroups), row split otherwise.
  *   NZSPLIT  : force the nonzero split (Sec. 4, scheme (a): the 1-D
  *              partition the paper's merge-based kernel implements) with
- *              default shapes. */
+ *              default shapes.
+ *   ROWBLOCK : force the row-block kernel (4 rows per block, default
+ *              shapes); SPMM_ERR_UNSUPPORTED unless every row's column
+ *              indices strictly increase and k < 2^24. AUTOTUNE also times
+ *              it when those hold, the longest row has at most 4096 entries
+ *              and blocks of 4 rows hold at most 85 % as many distinct
+ *              columns as entries. */
 typedef enum spmm_mode {
     SPMM_MODE_PAPER = 0,
     SPMM_MODE_AUTOTUNE = 1,
     SPMM_MODE_ROWSPLIT = 2,
     SPMM_MODE_MERGE = 3,
     SPMM_MODE_RULE = 4,
-    SPMM_MODE_NZSPLIT = 5
+    SPMM_MODE_NZSPLIT = 5,
+    SPMM_MODE_ROWBLOCK = 6
 } spmm_mode;
 
 /* ROWSPLIT: Sec. 4.1. MERGE: merge-based, pieces cut on the diagonals of
@@ -88,11 +95,20 @@ typedef enum spmm_mode {
  * nonzeros). NZSPLIT: merge-based, pieces cut by nonzero count (each piece
  * holds items_per_wg nonzeros and however many row ends fall among them,
  * found by a 1-D search on the row offsets): cheaper to partition, but a run
- * of empty rows lands in one piece and is written by one lane group. */
+ * of empty rows lands in one piece and is written by one lane group.
+ * ROWBLOCK (not in the paper; for matrices whose neighbouring rows share
+ * columns, such as stencils): row split over blocks of rows_per_block
+ * consecutive rows. The plan stores, per block, the sorted union of the
+ * block's columns (one 32-bit word per distinct column: the column and the
+ * set of the block's rows holding it, k * 4 bytes at most per row), and the
+ * kernel gathers each B row of the union once per block instead of once per
+ * entry. Only for the ordinary product: spmm_execute_semiring on such a plan
+ * runs row split with the same lane shape. */
 typedef enum spmm_kernel {
     SPMM_KERNEL_ROWSPLIT = 0,
     SPMM_KERNEL_MERGE = 1,
-    SPMM_KERNEL_NZSPLIT = 2
+    SPMM_KERNEL_NZSPLIT = 2,
+    SPMM_KERNEL_ROWBLOCK = 3
 } spmm_kernel;
 
 /* Semirings of spmm_execute_semiring: (add, multiply, identity). */
@@ -108,8 +124,9 @@ typedef struct spmm_config {
     int32_t kernel;        /* spmm_kernel */
     int32_t vec;           /* elements per lane per B-row access: 1, or the 16-byte width
                               (4 for float32, 8 for 16-bit types) */
-    int32_t lanes_per_row; /* row split (Sec. 4.1): lanes of a wavefront sharing one row of A,
-                              a power of two from the lanes one B row needs up to 64 */
+    int32_t lanes_per_row; /* row split (Sec. 4.1): lanes of a wavefront sharing one row of A
+                              (ROWBLOCK: one block of rows), a power of two from the lanes one
+                              B row needs up to 64 */
     int32_t unroll;        /* B-row gathers in flight per lane group: 1, 2, 4 or 8 */
     int32_t items_per_wg;  /* merge-based (Sec. 4.2): merge items (rows + nonzeros) per
                               workgroup, 64 .. 8192; NZSPLIT: nonzeros per workgroup */
@@ -117,6 +134,8 @@ typedef struct spmm_config {
                               vec; the product runs over ceil(n / tile_cols) tiles, each
                               re-reading A but touching only its columns of B. 0 = as wide as
                               one wavefront covers (64 * vec columns) */
+    int32_t rows_per_block;/* ROWBLOCK: rows per block, 2, 4 or 8 (0 = 4); other kernels
+                              ignore it */
 } spmm_config;
 
 typedef struct spmm_plan_info {
@@ -209,7 +228,7 @@ int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info_host);
  * MERGE: the states on diagonals min(p * W, m + nnz). NZSPLIT: (0, 0), then
  * j_p = min(p * W, nnz) with i_p the number of rows whose end is <= j_p,
  * and (m, nnz) last. cap is the capacity in pairs. Synchronous.
- * SPMM_ERR_STATE for row-split plans. */
+ * SPMM_ERR_STATE for row-split and row-block plans. */
 int spmm_plan_partition(spmm_plan_t plan, int32_t* coords_host, int64_t cap);
 
 /* Free the plan and its workspace (after the work queued with it is done:

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "plan.hpp"
+#include "rowblock.hpp"
 
 namespace spmmh {
 
@@ -96,6 +97,10 @@ static size_t lds_limit() {
     return lim;
 }
 
+static bool is_merge(int kernel) {
+    return kernel == SPMM_KERNEL_MERGE || kernel == SPMM_KERNEL_NZSPLIT;
+}
+
 int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const void* vals,
             const void* B, float* C, hipStream_t st, hipEvent_t ev_before, hipEvent_t ev_after,
             int semiring) {
@@ -103,11 +108,19 @@ int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const vo
     int vec = p.cfg.vec;
     if (vec != 1 && (!aligned16(B) || !aligned16(C))) vec = 1;
     const spmmk::Shape s = resolve_shape(p, vec);
-    const bool merge = p.cfg.kernel != SPMM_KERNEL_ROWSPLIT;
+    const bool merge = is_merge(p.cfg.kernel);
     if (merge && !p.ws.coords) return fail(SPMM_ERR_STATE, "merge plan without partition");
     const spmmk::ForwardArgs a{rowptr, colind, vals, B, C, p.m, p.n, p.ld,
                                p.ws.coords, p.ws.P, p.ws.carry_vals, p.ws.carry_rows};
     if (ev_before) SPMM_HIP(hipEventRecord(ev_before, st));
+    if (p.cfg.kernel == SPMM_KERNEL_ROWBLOCK && semiring == SPMM_PLUS_TIMES) {
+        if (!p.rb.ub_ptr) return fail(SPMM_ERR_STATE, "row-block plan without its structure");
+        const hipError_t e = spmmk::launch_rowblock(p.dtype, s, p.rb.R, a, p.rb.ub_ptr,
+                                                    p.rb.words, st, ev_after);
+        if (e != hipSuccess) return hip_fail(e, "row-block launch");
+        return SPMM_OK;
+    }
+    // (other semirings on a row-block plan run row split with its lane shape)
     const hipError_t e =
         semiring == SPMM_PLUS_TIMES
             ? spmmk::launch_forward_plus_times(p.dtype, merge, s, a, st, ev_after)
@@ -151,12 +164,84 @@ static int prepare_merge(const spmm_plan_s& p, MergeWs& ws, int W, bool nz, hipS
     return SPMM_OK;
 }
 
+static void free_rb(RowBlocks& rb) {
+    if (rb.ub_ptr) (void)hipFree(rb.ub_ptr);
+    if (rb.words) (void)hipFree(rb.words);
+    rb = RowBlocks{};
+}
+
+// Whether every row's column indices strictly increase (once per plan).
+static int ensure_sorted(spmm_plan_s& p, hipStream_t st) {
+    if (p.sorted >= 0) return SPMM_OK;
+    if (p.m == 0 || p.nnz == 0) {
+        p.sorted = 1;
+        return SPMM_OK;
+    }
+    int* d = nullptr;
+    int h = 0;
+    SPMM_HIP(hipMalloc(&d, sizeof(int)));
+    hipError_t e = hipMemsetAsync(d, 0, sizeof(int), st);
+    if (e == hipSuccess) e = spmmk::launch_rowblock_check_sorted(p.rowptr, p.colind, p.m, d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "row order check");
+    p.sorted = h ? 0 : 1;
+    return SPMM_OK;
+}
+
+// Build the row-block structure for blocks of R rows: union sizes, their
+// scan, then the union words. One host sync (the total size).
+static int prepare_rowblock(const spmm_plan_s& p, RowBlocks& rb, int R, hipStream_t st) {
+    if (rb.ub_ptr && rb.R == R) return SPMM_OK;
+    free_rb(rb);
+    const int64_t mb = (p.m + R - 1) / R;
+    int* sums = nullptr;
+    hipError_t e = hipMalloc(&rb.ub_ptr, sizeof(int) * (mb + 1));
+    if (e == hipSuccess)
+        e = hipMalloc(&sums, sizeof(int) * std::max<int64_t>(1, spmmk::scan_chunks(mb + 1)));
+    if (e == hipSuccess) e = hipMemsetAsync(rb.ub_ptr + mb, 0, sizeof(int), st);
+    if (e == hipSuccess)
+        e = spmmk::launch_rowblock_union(p.rowptr, p.colind, p.m, R, nullptr, rb.ub_ptr, st);
+    if (e == hipSuccess) e = spmmk::exclusive_scan_i32(rb.ub_ptr, mb + 1, sums, st);
+    int total = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&total, rb.ub_ptr + mb, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (sums) (void)hipFree(sums);
+    if (e == hipSuccess) e = hipMalloc(&rb.words, sizeof(int) * std::max(1, total));
+    if (e == hipSuccess)
+        e = spmmk::launch_rowblock_union(p.rowptr, p.colind, p.m, R, rb.ub_ptr, rb.words, st);
+    if (e != hipSuccess) {
+        free_rb(rb);
+        return hip_fail(e, "row-block structure");
+    }
+    rb.mb = mb;
+    rb.U = total;
+    rb.R = R;
+    return SPMM_OK;
+}
+
 static int check_config(const spmm_plan_s& p, spmm_config& c) {
     const int v16 = vec16(p.dtype);
     const bool can16 = (p.n % v16 == 0) && (p.ld % v16 == 0);
     if (c.kernel != SPMM_KERNEL_ROWSPLIT && c.kernel != SPMM_KERNEL_MERGE &&
-        c.kernel != SPMM_KERNEL_NZSPLIT)
+        c.kernel != SPMM_KERNEL_NZSPLIT && c.kernel != SPMM_KERNEL_ROWBLOCK)
         return fail(SPMM_ERR_INVALID, "config.kernel %d is not a kernel", c.kernel);
+    if (c.kernel == SPMM_KERNEL_ROWBLOCK) {
+        if (c.rows_per_block == 0) c.rows_per_block = 4;
+        if (c.rows_per_block != 2 && c.rows_per_block != 4 && c.rows_per_block != 8)
+            return fail(SPMM_ERR_UNSUPPORTED, "config.rows_per_block %d: use 2, 4 or 8",
+                        c.rows_per_block);
+        if (p.k >= (int64_t(1) << spmmk::kRowBlockColBits))
+            return fail(SPMM_ERR_UNSUPPORTED, "row-block kernel needs k < 2^24 (k = %lld)",
+                        (long long)p.k);
+        if (p.sorted != 1)
+            return fail(SPMM_ERR_UNSUPPORTED,
+                        "row-block kernel needs strictly increasing column indices in every row");
+    } else {
+        c.rows_per_block = 0;
+    }
     if (c.vec == 0) c.vec = can16 ? v16 : 1;
     if (c.vec != 1 && c.vec != v16)
         return fail(SPMM_ERR_UNSUPPORTED, "config.vec %d: use 1 or %d for this dtype", c.vec, v16);
@@ -189,7 +274,7 @@ static int check_config(const spmm_plan_s& p, spmm_config& c) {
     }
     if (c.items_per_wg < 64 || c.items_per_wg > 8192)
         return fail(SPMM_ERR_UNSUPPORTED, "config.items_per_wg %d outside 64..8192", c.items_per_wg);
-    if (c.kernel != SPMM_KERNEL_ROWSPLIT) {
+    if (is_merge(c.kernel)) {
         spmmk::Shape s;
         s.vec = c.vec;
         s.W = c.items_per_wg;
@@ -209,16 +294,18 @@ struct TuneKey {
     int device;
     int64_t m, k, nnz, n, ld, maxrow, longrows;
     int dtype, unroll, max_W;
+    bool rowblock;
     bool operator<(const TuneKey& o) const {
-        return std::tie(device, m, k, nnz, n, ld, maxrow, longrows, dtype, unroll, max_W) <
+        return std::tie(device, m, k, nnz, n, ld, maxrow, longrows, dtype, unroll, max_W,
+                        rowblock) <
                std::tie(o.device, o.m, o.k, o.nnz, o.n, o.ld, o.maxrow, o.longrows, o.dtype,
-                        o.unroll, o.max_W);
+                        o.unroll, o.max_W, o.rowblock);
     }
 };
 static std::map<TuneKey, std::pair<spmm_config, double>> g_tuned;
 
 static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_unroll,
-                                                int max_W) {
+                                                int max_W, bool rowblock) {
     std::vector<spmm_config> out;
     const int v16 = vec16(p.dtype);
     const int vec = (p.n % v16 == 0 && p.ld % v16 == 0) ? v16 : 1;
@@ -255,6 +342,17 @@ static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_
         for (int lpr = spmmk::kWaveSize; lpr >= (1 << g_log2); lpr /= 2)
             for (int u : unrolls) out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024, tc});
     }
+    // Row blocks last: chosen only when faster than every kernel of the paper
+    // by more than the tie margin.
+    if (rowblock)
+        for (int R : {4, 8})
+            for (int tc : tiles) {
+                int g_log2, nt;
+                slot_geometry(p.n, vec, &g_log2, &nt, tc);
+                for (int lpr = spmmk::kWaveSize; lpr >= (1 << g_log2); lpr /= 2)
+                    for (int u : unrolls)
+                        out.push_back({SPMM_KERNEL_ROWBLOCK, vec, lpr, u, 1024, tc, R});
+            }
     return out;
 }
 
@@ -263,13 +361,28 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     const int max_W = opts ? opts->max_W : 0;
     const bool own = opts && opts->C && (p.nnz == 0 || (opts->vals && opts->B));
     const TuneKey key{p.device, p.m, p.k, p.nnz, p.n, p.ld, p.max_row_len, p.long_rows, p.dtype,
-                      fixed_unroll, max_W};
+                      fixed_unroll, max_W, !opts || opts->rowblock};
     {
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_tuned.find(key);
-        if (it != g_tuned.end()) {
-            p.cfg = it->second.first;
-            p.tuned_ms = it->second.second;
+        std::pair<spmm_config, double> hit{};
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) {
+                hit = it->second;
+                found = true;
+            }
+        }
+        // A cached row-block choice holds only for a matrix with sorted rows
+        // (the key does not see the order of columns): else tune afresh.
+        if (found && hit.first.kernel == SPMM_KERNEL_ROWBLOCK) {
+            const int rc0 = ensure_sorted(p, st);
+            if (rc0 != SPMM_OK) return rc0;
+            found = p.sorted == 1;
+        }
+        if (found) {
+            p.cfg = hit.first;
+            p.tuned_ms = hit.second;
             return SPMM_OK;
         }
     }
@@ -284,6 +397,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     const void* use_B = own ? opts->B : nullptr;
     float* use_C = own ? opts->C : nullptr;
     MergeWs ws;
+    RowBlocks rb4, rb8;  // row-block structures of the candidates
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SPMM_OK;
     auto cleanup = [&]() {
@@ -291,6 +405,8 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
         if (B) (void)hipFree(B);
         if (C) (void)hipFree(C);
         free_ws(ws);
+        free_rb(rb4);
+        free_rb(rb8);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
@@ -316,6 +432,22 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     TUNE_HIP(hipEventCreate(&e0));
     TUNE_HIP(hipEventCreate(&e1));
 
+    // The row-block kernel is a candidate for sorted rows of moderate length
+    // whose blocks of 4 rows share enough columns to save gathers.
+    bool rowblock = (!opts || opts->rowblock) && p.nnz > 0 &&
+                    p.k < (int64_t(1) << spmmk::kRowBlockColBits) && p.max_row_len <= 4096;
+    if (rowblock) {
+        rc = ensure_sorted(p, st);
+        if (rc != SPMM_OK) { cleanup(); return rc; }
+        rowblock = p.sorted == 1;
+    }
+    if (rowblock) {
+        rc = prepare_rowblock(p, rb4, 4, st);
+        if (rc != SPMM_OK) { cleanup(); return rc; }
+        rowblock = double(rb4.U) <= 0.85 * double(p.nnz);
+        if (!rowblock) free_rb(rb4);
+    }
+
     // Candidates within kTie (1.5 %, above the run-to-run spread of the
     // median) of the fastest count as equal; the earliest in
     // candidate order wins, so repeated tuning of one matrix picks one shape.
@@ -323,16 +455,23 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     double best = 1e30;
     std::vector<std::pair<spmm_config, double>> timed;
     int slow_rowsplit = 0;
-    for (spmm_config c : tune_candidates(p, fixed_unroll, max_W)) {
-        if (c.kernel == SPMM_KERNEL_ROWSPLIT && slow_rowsplit >= 3) break;
+    for (spmm_config c : tune_candidates(p, fixed_unroll, max_W, rowblock)) {
+        if (c.kernel == SPMM_KERNEL_ROWSPLIT && slow_rowsplit >= 3) continue;
         spmm_plan_s q = p;  // shallow copy: never destroyed
         q.ws = MergeWs{};
+        q.rb = RowBlocks{};
         if (check_config(q, c) != SPMM_OK) continue;
         q.cfg = c;
-        if (c.kernel != SPMM_KERNEL_ROWSPLIT) {
+        if (is_merge(c.kernel)) {
             rc = prepare_merge(q, ws, c.items_per_wg, c.kernel == SPMM_KERNEL_NZSPLIT, st);
             if (rc != SPMM_OK) { cleanup(); return rc; }
             q.ws = ws;
+        }
+        if (c.kernel == SPMM_KERNEL_ROWBLOCK) {
+            RowBlocks& rb = c.rows_per_block == 4 ? rb4 : rb8;
+            rc = prepare_rowblock(p, rb, c.rows_per_block, st);
+            if (rc != SPMM_OK) { cleanup(); return rc; }
+            q.rb = rb;
         }
         std::vector<float> times;
         for (int rep = 0; rep < 6; ++rep) {
@@ -364,6 +503,13 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
             best_ms = t.second;
             break;
         }
+    }
+    if (best_cfg.kernel == SPMM_KERNEL_ROWBLOCK && best_ms < 1e30) {
+        // hand the chosen structure to the plan
+        RowBlocks& rb = best_cfg.rows_per_block == 4 ? rb4 : rb8;
+        free_rb(p.rb);
+        p.rb = rb;
+        rb = RowBlocks{};
     }
     cleanup();
 #undef TUNE_HIP
@@ -422,6 +568,7 @@ void destroy_plan(spmm_plan_s* p) {
     (void)hipDeviceSynchronize();
     free_ws(p->ws);
     free_ws(p->sddmm_ws);
+    free_rb(p->rb);
     if (p->tr.at_rowptr) (void)hipFree(p->tr.at_rowptr);
     if (p->tr.at_colind) (void)hipFree(p->tr.at_colind);
     if (p->tr.perm) (void)hipFree(p->tr.perm);
@@ -440,7 +587,7 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
     if (rc) return rc;
     if (dtype != SPMM_F32 && dtype != SPMM_BF16 && dtype != SPMM_F16)
         return fail(SPMM_ERR_UNSUPPORTED, "dtype %d", dtype);
-    if (!forced && (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_NZSPLIT))
+    if (!forced && (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_ROWBLOCK))
         return fail(SPMM_ERR_INVALID, "mode %d", mode);
     if (m > 0 && !rowptr) return fail(SPMM_ERR_INVALID, "A_rowptr is NULL");
     if (nnz > 0 && !colind) return fail(SPMM_ERR_INVALID, "A_colind is NULL");
@@ -458,6 +605,9 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
     if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
 
     rc = row_stats(*p, st);
+    const bool want_rowblock = forced ? forced->kernel == SPMM_KERNEL_ROWBLOCK
+                                      : mode == SPMM_MODE_ROWBLOCK;
+    if (rc == SPMM_OK && want_rowblock) rc = ensure_sorted(*p, st);
     if (rc == SPMM_OK) {
         if (forced) {
             p->cfg = *forced;
@@ -469,6 +619,7 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
                              : mode == SPMM_MODE_RULE    ? rule_choice(*p)
                              : mode == SPMM_MODE_MERGE   ? SPMM_KERNEL_MERGE
                              : mode == SPMM_MODE_NZSPLIT ? SPMM_KERNEL_NZSPLIT
+                             : mode == SPMM_MODE_ROWBLOCK ? SPMM_KERNEL_ROWBLOCK
                                                           : SPMM_KERNEL_ROWSPLIT;
             p->cfg = spmm_config{kern, 0, 0, opts ? opts->fixed_unroll : 0, 0, 0};
             rc = check_config(*p, p->cfg);
@@ -476,9 +627,11 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
     }
     if (rc == SPMM_OK && opts && opts->max_W && p->cfg.items_per_wg > opts->max_W)
         p->cfg.items_per_wg = opts->max_W;
-    if (rc == SPMM_OK && p->cfg.kernel != SPMM_KERNEL_ROWSPLIT)
+    if (rc == SPMM_OK && is_merge(p->cfg.kernel))
         rc = prepare_merge(*p, p->ws, p->cfg.items_per_wg, p->cfg.kernel == SPMM_KERNEL_NZSPLIT,
                            st);
+    if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_ROWBLOCK && p->m > 0)
+        rc = prepare_rowblock(*p, p->rb, p->cfg.rows_per_block, st);
     // SDDMM walks diagonal merge pieces (their row ends fit its LDS); other
     // plans get such a partition for it.
     if (rc == SPMM_OK && p->cfg.kernel != SPMM_KERNEL_MERGE && p->m > 0 && p->nnz > 0)
@@ -593,7 +746,7 @@ int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info) {
     const spmmk::Shape s = resolve_shape(*plan, plan->cfg.vec);
     info->lanes_per_slot = 1 << s.g_log2;
     info->col_tiles = s.col_tiles;
-    info->num_parts = plan->cfg.kernel != SPMM_KERNEL_ROWSPLIT ? plan->ws.P : 0;
+    info->num_parts = is_merge(plan->cfg.kernel) ? plan->ws.P : 0;
     info->max_row_len = plan->max_row_len;
     info->mean_row_len = plan->m ? double(plan->nnz) / double(plan->m) : 0.0;
     info->tuned_ms = plan->tuned_ms;
@@ -603,8 +756,8 @@ int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info) {
 
 int spmm_plan_partition(spmm_plan_t plan, int32_t* coords_host, int64_t cap) {
     if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
-    if (plan->cfg.kernel == SPMM_KERNEL_ROWSPLIT)
-        return fail(SPMM_ERR_STATE, "row-split plan has no merge partition");
+    if (!is_merge(plan->cfg.kernel))
+        return fail(SPMM_ERR_STATE, "row-split or row-block plan has no merge partition");
     if (!coords_host) return fail(SPMM_ERR_INVALID, "coords_host is NULL");
     if (cap < plan->ws.P + 1)
         return fail(SPMM_ERR_INVALID, "cap %lld < P + 1 = %lld", (long long)cap,

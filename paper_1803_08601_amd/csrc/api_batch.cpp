@@ -106,6 +106,7 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
         TuneOpts opts;
         opts.fixed_unroll = spmmk::kBatchUnroll;
         opts.max_W = spmmk::kBatchMaxW;
+        opts.rowblock = false;  // the persistent kernel runs row split and merge tiles only
         opts.vals = q.A_vals;
         opts.B = q.B;
         opts.C = q.C;

@@ -10,6 +10,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "rowblock.hpp"
 
 namespace spmmk {
 
@@ -147,6 +148,10 @@ static hipError_t exclusive_scan(int* a, int64_t len, int* sums, hipStream_t st)
     hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, sums, nb);
     hipLaunchKernelGGL(k_scan_chunks, dim3((uint32_t)nb), dim3(kBlock), 0, st, a, len, sums);
     return hipGetLastError();
+}
+
+hipError_t exclusive_scan_i32(int* a, int64_t len, int* sums, hipStream_t st) {
+    return exclusive_scan(a, len, sums, st);
 }
 
 // Stable scatter of one digit pass, carrying two value arrays (entry

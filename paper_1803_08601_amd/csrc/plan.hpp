@@ -31,6 +31,15 @@ struct MergeWs {
     int64_t cap_n = 0;
 };
 
+// Row-block structure: union offsets (one per block of R rows, plus one)
+// and union words (column | row set << 24).
+struct RowBlocks {
+    int* ub_ptr = nullptr;
+    int* words = nullptr;
+    int64_t mb = 0, U = 0;
+    int R = 0;
+};
+
 struct Transpose {
     int* at_rowptr = nullptr;
     int* at_colind = nullptr;
@@ -51,6 +60,8 @@ struct spmm_plan_s {
     int device = 0;
     spmmh::MergeWs ws;
     spmmh::MergeWs sddmm_ws;  // merge partition for SDDMM when the kernel is row split
+    spmmh::RowBlocks rb;      // ROWBLOCK plans
+    int sorted = -1;          // columns strictly increase in every row: 1 / 0 / -1 unknown
     spmmh::Transpose tr;
     spmm_plan_s* tplan = nullptr;  // plan over A^T (k rows, m columns)
 };
@@ -75,6 +86,7 @@ int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const vo
 struct TuneOpts {
     int fixed_unroll = 0;
     int max_W = 0;  // largest merge piece allowed (0: no limit)
+    bool rowblock = true;  // the row-block kernel may be a candidate
     const void* vals = nullptr;
     const void* B = nullptr;
     float* C = nullptr;

@@ -18,21 +18,22 @@ SPMM_OK, SPMM_ERR_INVALID, SPMM_ERR_UNSUPPORTED, SPMM_ERR_HIP, SPMM_ERR_NOMEM, S
     0, -1, -2, -3, -4, -5
 SPMM_F32, SPMM_BF16, SPMM_F16 = 0, 1, 2
 SPMM_MODE_PAPER, SPMM_MODE_AUTOTUNE, SPMM_MODE_ROWSPLIT, SPMM_MODE_MERGE, SPMM_MODE_RULE = 0, 1, 2, 3, 4
-SPMM_MODE_NZSPLIT = 5
-SPMM_KERNEL_ROWSPLIT, SPMM_KERNEL_MERGE, SPMM_KERNEL_NZSPLIT = 0, 1, 2
+SPMM_MODE_NZSPLIT, SPMM_MODE_ROWBLOCK = 5, 6
+SPMM_KERNEL_ROWSPLIT, SPMM_KERNEL_MERGE, SPMM_KERNEL_NZSPLIT, SPMM_KERNEL_ROWBLOCK = 0, 1, 2, 3
 SPMM_PLUS_TIMES, SPMM_MIN_PLUS, SPMM_MAX_PLUS, SPMM_MAX_TIMES = 0, 1, 2, 3
 
 MODES = {"paper": SPMM_MODE_PAPER, "autotune": SPMM_MODE_AUTOTUNE,
          "rowsplit": SPMM_MODE_ROWSPLIT, "merge": SPMM_MODE_MERGE, "rule": SPMM_MODE_RULE,
-         "nzsplit": SPMM_MODE_NZSPLIT}
+         "nzsplit": SPMM_MODE_NZSPLIT, "rowblock": SPMM_MODE_ROWBLOCK}
 KERNEL_NAMES = {SPMM_KERNEL_ROWSPLIT: "rowsplit", SPMM_KERNEL_MERGE: "merge",
-                SPMM_KERNEL_NZSPLIT: "nzsplit"}
+                SPMM_KERNEL_NZSPLIT: "nzsplit", SPMM_KERNEL_ROWBLOCK: "rowblock"}
 
 
 class spmm_config(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("vec", ctypes.c_int32),
                 ("lanes_per_row", ctypes.c_int32), ("unroll", ctypes.c_int32),
-                ("items_per_wg", ctypes.c_int32), ("tile_cols", ctypes.c_int32)]
+                ("items_per_wg", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
+                ("rows_per_block", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -74,6 +74,31 @@ def test_spmm_csr_noop_and_checks():
     assert L.spmm_csr(None, None, None, None, None, -1, 5, 4, 4, None) == nv.SPMM_ERR_INVALID
 
 
-def test_config_struct_layout():
-    assert ctypes.sizeof(nv.spmm_config) == 24
+def test_config_struct_layout(tmp_path):
+    """The ctypes structures match the C header's layout: a C program built
+    against include/spmm.h prints every field's offset and each size."""
+    import shutil
+    import subprocess
+    assert ctypes.sizeof(nv.spmm_config) == 28
     assert ctypes.sizeof(nv.spmm_problem) == 5 * 8 + 5 * 8
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"spmm_config": nv.spmm_config, "spmm_plan_info": nv.spmm_plan_info,
+               "spmm_problem": nv.spmm_problem}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{nv.HEADER}"',
+             "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = dict(ln.split() for ln in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                   check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(out[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"

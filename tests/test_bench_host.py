@@ -34,6 +34,9 @@ def test_counter_lookup_needs_same_shape_and_sources():
     assert bench.counter_traffic(recs, "other", cfg) is None
     stale = {"w": [dict(rec, kernel_source_sha="0" * 16)]}
     assert bench.counter_traffic(stale, "w", cfg) is None
+    # a shape field added after the counters were taken matches only at its default
+    assert bench.counter_traffic(recs, "w", dict(cfg, rows_per_block=0)) is not None
+    assert bench.counter_traffic(recs, "w", dict(cfg, rows_per_block=4)) is None
 
 
 def test_committed_counter_records_are_well_formed():

@@ -1,8 +1,8 @@
 """Every launch shape a plan can take, against the FP64 oracle.
 
 The autotuner and the batch planner may pick any valid combination of kernel
-(row split, merge path, nonzero split), vector width, lanes per row, unroll,
-merge items per workgroup and column tile; each is a separate code path in
+(row split, merge path, nonzero split, row blocks), vector width, lanes per
+row, unroll, merge items per workgroup, rows per block and column tile; each is a separate code path in
 the kernels (template instantiations plus the runtime slot geometry). This
 sweep runs all of them on one ragged matrix: empty rows, rows of every short
 length, rows whose length is not a multiple of any slot count, and long rows
@@ -19,6 +19,7 @@ from spmm_check import TOL_F32, TOL_STORAGE_16, dev, oracle_product, rel_err
 pytestmark = pytest.mark.gpu
 
 RS, MG, NZ = nv.SPMM_KERNEL_ROWSPLIT, nv.SPMM_KERNEL_MERGE, nv.SPMM_KERNEL_NZSPLIT
+RB = nv.SPMM_KERNEL_ROWBLOCK
 VEC16 = {torch.float32: 4, torch.bfloat16: 8}
 
 
@@ -49,6 +50,10 @@ def configs(n, dtype):
                 for kern in (MG, NZ):
                     for W in (64, 100, 1000, 4096):
                         yield dict(kernel=kern, vec=vec, items_per_wg=W, unroll=u, tile_cols=tc)
+                for R in (2, 4, 8):
+                    for lanes in (1, 4, 16, 64):
+                        yield dict(kernel=RB, vec=vec, lanes_per_row=lanes, unroll=u,
+                                   tile_cols=tc, rows_per_block=R)
 
 
 @pytest.fixture(scope="module")
@@ -99,7 +104,7 @@ def test_sddmm_every_launch_shape(matrix, dtype, n):
     N = oracle.sddmm(A.rowptr, A.colind, dC, b, b_tag=btag, absval=True)
     v16 = VEC16[dtype]
     shapes = [dict(kernel=MG, items_per_wg=W) for W in (64, 100, 1000, 4096)]
-    shapes += [dict(kernel=RS), dict(kernel=NZ, items_per_wg=1000)]
+    shapes += [dict(kernel=RS), dict(kernel=NZ, items_per_wg=1000), dict(kernel=RB)]
     dv = torch.empty(A.nnz, device="cuda")
     ran = 0
     for vec in [1] + ([v16] if n % v16 == 0 else []):

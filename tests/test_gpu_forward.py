@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 RS = nv.SPMM_KERNEL_ROWSPLIT
 MG = nv.SPMM_KERNEL_MERGE
 NZ = nv.SPMM_KERNEL_NZSPLIT
+RB = nv.SPMM_KERNEL_ROWBLOCK
 
 
 def _upload(A):
@@ -54,12 +55,16 @@ CONFIGS = [
     dict(kernel=NZ, items_per_wg=2048, unroll=4),
     dict(kernel=NZ, items_per_wg=4096, unroll=8),
     dict(kernel=NZ, items_per_wg=512, unroll=4, tile_cols=32),
+    dict(kernel=RB, rows_per_block=2, lanes_per_row=16, unroll=2),
+    dict(kernel=RB, rows_per_block=4, unroll=4),
+    dict(kernel=RB, rows_per_block=8, lanes_per_row=64, unroll=8),
+    dict(kernel=RB, rows_per_block=4, lanes_per_row=8, unroll=1, tile_cols=32),
 ]
 
 
 def cfg_id(c):
     return (f"{nv.KERNEL_NAMES[c['kernel']]}-{c.get('lanes_per_row', c.get('items_per_wg'))}"
-            f"-u{c['unroll']}-t{c.get('tile_cols', 0)}")
+            f"-u{c['unroll']}-t{c.get('tile_cols', 0)}-r{c.get('rows_per_block', 0)}")
 
 
 @pytest.mark.parametrize("cfg", CONFIGS, ids=cfg_id)
@@ -71,7 +76,7 @@ def test_plain_configs(cfg, n):
     check(A, dev(A.vals), dev(B), n, C)
 
 
-@pytest.mark.parametrize("mode", ["paper", "rowsplit", "merge", "nzsplit", "autotune"])
+@pytest.mark.parametrize("mode", ["paper", "rowsplit", "merge", "nzsplit", "rowblock", "autotune"])
 def test_power_law_modes(mode):
     A = wl.power_law(seed=31, m=40_000, cap=20_000)
     for n in (8, 64):
@@ -84,15 +89,19 @@ def test_power_law_modes(mode):
             assert info.config.kernel == MG
         if mode == "nzsplit":
             assert info.config.kernel == NZ
+        if mode == "rowblock":
+            assert info.config.kernel == RB and info.config.rows_per_block == 4
 
 
-@pytest.mark.parametrize("mode", ["rowsplit", "merge", "nzsplit"])
+@pytest.mark.parametrize("mode", ["rowsplit", "merge", "nzsplit", "rowblock", "autotune"])
 def test_stencil_modes(mode):
     A = wl.stencil27(g=24)
     for n in (16, 128):
         B = wl.dense(1003, A.k, n)
-        C, _ = run(A, dev(A.vals), dev(B), n, mode=mode)
+        C, plan = run(A, dev(A.vals), dev(B), n, mode=mode)
         check(A, dev(A.vals), dev(B), n, C)
+        if mode == "rowblock":
+            assert plan.info().config.kernel == RB
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
@@ -110,7 +119,7 @@ def test_integer_exact(dtype, cfg):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("kernel", [RS, MG, NZ])
+@pytest.mark.parametrize("kernel", [RS, MG, NZ, RB])
 def test_identity_permutation_diagonal_bitwise(kernel, dtype):
     """One product per output element, no additions: A = I gives B, a
     permutation gives B[pi], a diagonal gives diag * B, bit for bit (the
@@ -132,7 +141,7 @@ def test_identity_permutation_diagonal_bitwise(kernel, dtype):
         assert np.array_equal(C.cpu().numpy(), expect)
 
 
-@pytest.mark.parametrize("kernel", [RS, MG, NZ])
+@pytest.mark.parametrize("kernel", [RS, MG, NZ, RB])
 def test_power_of_two_scaling_and_empty_rows_bitwise(kernel):
     """(2^e A) B equals 2^e (A B) bit for bit (scaling by a power of two is
     exact and the plan fixes the summation order), and every empty row is
@@ -192,7 +201,8 @@ def test_nz_partition_bit_exact_and_product(name, W):
 def test_row_sum_invariant_and_determinism():
     A = wl.power_law(seed=12, m=20_000, cap=20_000, values="uniform")
     ones = np.ones((A.k, 32), np.float32)
-    for cfg in (dict(kernel=RS), dict(kernel=MG, items_per_wg=512), dict(kernel=NZ, items_per_wg=512)):
+    for cfg in (dict(kernel=RS), dict(kernel=MG, items_per_wg=512), dict(kernel=NZ, items_per_wg=512),
+                dict(kernel=RB, rows_per_block=8)):
         C1, plan = run(A, dev(A.vals), dev(ones), 32, config=cfg)
         C2 = torch.empty_like(C1)
         plan.execute(dev(A.vals), dev(ones), C2)
@@ -222,13 +232,84 @@ EDGE = {
 
 
 @pytest.mark.parametrize("name", sorted(EDGE))
-@pytest.mark.parametrize("kernel", [RS, MG, NZ])
+@pytest.mark.parametrize("kernel", [RS, MG, NZ, RB])
 @pytest.mark.parametrize("n", [3, 16, 260])
 def test_edge_cases(name, kernel, n):
     A = EDGE[name]
     B = wl.dense(9, max(A.k, 1), n)
+    if kernel == RB and name == "dups":  # repeated columns in a row: refused
+        with pytest.raises(nv.SpmmError) as ei:
+            run(A, dev(A.vals), dev(B), n, config=dict(kernel=kernel))
+        assert ei.value.status == nv.SPMM_ERR_UNSUPPORTED
+        return
     C, _ = run(A, dev(A.vals), dev(B), n, config=dict(kernel=kernel, items_per_wg=128))
     check(A, dev(A.vals), dev(B), n, C)
+
+
+def test_rowblock_terms_refusals_and_other_entry_points():
+    """Row blocks: a row without a column takes no term for it (an infinite
+    B row reaches only the rows that hold its column); rows whose columns do
+    not strictly increase, or k >= 2^24, are refused, and timing then picks
+    another kernel; semiring products, SDDMM and dB run on a row-block plan."""
+    A = wl.stencil27(g=12)
+    n = 16
+    B = wl.dense(41, A.k, n)
+    cstar = 5 + 12 * 6 + 144 * 6
+    B[cstar, :] = np.inf
+    for R in (2, 4, 8):
+        C, plan = run(A, dev(A.vals), dev(B), n, config=dict(kernel=RB, rows_per_block=R))
+        c = C.cpu().numpy()
+        holds = np.zeros(A.m, bool)
+        rows = np.repeat(np.arange(A.m), A.row_lengths())
+        holds[rows[A.colind == cstar]] = True
+        assert holds.sum() == 27 and np.all(np.isinf(c[holds]))
+        Bf = B.copy()
+        Bf[cstar, :] = 0.0
+        Cref, N = oracle_product(A.rowptr, A.colind, dev(A.vals), dev(Bf), n)
+        assert rel_err(c[~holds], Cref[~holds], N[~holds]) <= TOL_F32
+        with pytest.raises(nv.SpmmError):
+            plan.partition()
+    # unsorted rows: refused when forced, another kernel when timed
+    U = wl.random_csr(42, 800, 500, density=0.05)
+    ci = U.colind.copy()
+    r = int(np.argmax(U.row_lengths()))
+    ci[U.rowptr[r]:U.rowptr[r + 1]] = ci[U.rowptr[r]:U.rowptr[r + 1]][::-1]
+    Uu = wl.CSR(U.rowptr, ci, U.vals, U.m, U.k)
+    Bu = wl.dense(43, U.k, 32)
+    with pytest.raises(nv.SpmmError) as ei:
+        run(Uu, dev(Uu.vals), dev(Bu), 32, mode="rowblock")
+    assert ei.value.status == nv.SPMM_ERR_UNSUPPORTED
+    C, plan = run(Uu, dev(Uu.vals), dev(Bu), 32, mode="autotune")
+    assert plan.info().config.kernel != RB
+    check(Uu, dev(Uu.vals), dev(Bu), 32, C)
+    # k >= 2^24: refused before any launch
+    big = wl.CSR(np.array([0, 1], np.int32), np.array([(1 << 24) + 5], np.int32),
+                 np.ones(1, np.float32), 1, (1 << 24) + 10)
+    with pytest.raises(nv.SpmmError) as ei:
+        nv.Plan(dev(big.rowptr), dev(big.colind), 1, big.k, 4, config=dict(kernel=RB), nnz=1)
+    assert ei.value.status == nv.SPMM_ERR_UNSUPPORTED
+    # semiring, SDDMM and dB on a row-block plan
+    S = wl.stencil27(g=10)
+    n = 24
+    Bs = wl.dense(44, S.k, n)
+    dC = wl.dense(45, S.m, n, kind="normal")
+    plan = nv.Plan(dev(S.rowptr), dev(S.colind), S.m, S.k, n, config=dict(kernel=RB), nnz=S.nnz)
+    Cm = torch.empty(S.m, n, device="cuda")
+    plan.execute_semiring(nv.SPMM_MIN_PLUS, dev(S.vals), dev(Bs), Cm)
+    plan.transpose_build()
+    dB = torch.empty(S.k, n, device="cuda")
+    dv = torch.empty(S.nnz, device="cuda")
+    plan.execute_t(dev(S.vals), dev(dC), dB)
+    plan.sddmm(dev(dC), dev(Bs), dv)
+    torch.cuda.synchronize()
+    ref = oracle.spmm_semiring(S.rowptr, S.colind, S.vals, Bs, oracle.MIN_PLUS)
+    assert np.array_equal(Cm.cpu().numpy(), ref.astype(np.float32))  # min and + are exact here
+    rdB = oracle.spmm_t(S.rowptr, S.colind, S.vals, dC, S.k)
+    NdB = oracle.spmm_t(S.rowptr, S.colind, S.vals, dC, S.k, absval=True)
+    assert rel_err(dB.cpu().numpy(), rdB, NdB) <= TOL_F32
+    rdv = oracle.sddmm(S.rowptr, S.colind, dC, Bs)
+    Ndv = oracle.sddmm(S.rowptr, S.colind, dC, Bs, absval=True)
+    assert rel_err(dv.cpu().numpy(), rdv, Ndv) <= TOL_F32
 
 
 @pytest.mark.parametrize("kernel", [RS, MG, NZ])

@@ -72,11 +72,14 @@ def test_stencil_full(stencil, n):
     A = stencil
     B = wl.dense(1003, A.k, n)
     rp, ci, vt, Bt = dev(A.rowptr), dev(A.colind), dev(A.vals), dev(B)
-    for mode in ("autotune", "paper"):
-        plan = nv.Plan(rp, ci, A.m, A.k, n, mode=mode, nnz=A.nnz)
+    for mode in ("autotune", "paper", "rowblock", dict(kernel=nv.SPMM_KERNEL_ROWBLOCK,
+                                                      rows_per_block=8)):
+        cfg = mode if isinstance(mode, dict) else None
+        plan = nv.Plan(rp, ci, A.m, A.k, n, mode="paper" if cfg else mode, config=cfg, nnz=A.nnz)
         C = torch.full((A.m, n), float("nan"), device="cuda")
         plan.execute(vt, Bt, C)
         torch.cuda.synchronize()
+        assert not torch.isnan(C).any()
         check_rows(A, vt, Bt, C, n, sample_rows(A))
         del plan
 
@@ -91,7 +94,7 @@ def test_power_law_integer_exact_full(power_law):
     B = wl.dense(3, A.k, n, kind="int")
     rp, ci = dev(A.rowptr), dev(A.colind)
     ref = oracle.spmm(A.rowptr, A.colind, A.vals, B)
-    for mode in ("merge", "rowsplit", "nzsplit"):
+    for mode in ("merge", "rowsplit", "nzsplit", "rowblock"):
         plan = nv.Plan(rp, ci, A.m, A.k, n, mode=mode, nnz=A.nnz)
         C = torch.empty(A.m, n, device="cuda")
         plan.execute(dev(A.vals), dev(B), C)
