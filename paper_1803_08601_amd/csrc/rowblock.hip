@@ -141,6 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_rowblock(const int* __restrict__ row
     const uint64_t tmask = (TL == kWave ? ~0ull : ((1ull << TL) - 1)) << team_base;
     const uint64_t below = (1ull << lane) - 1;
     const int CH = 2 * TL;
+    const int TS = 1 << ts_log2;  // slots per team
 
     auto b_row = [&](uint32_t c) -> const typename S::T* {
         if constexpr (SHORT) {
@@ -203,42 +204,59 @@ __global__ __launch_bounds__(kBlock) void k_rowblock(const int* __restrict__ row
                     v1[r] = h1 ? load_elem(vals + cur[r] + n0 + __popcll(m1 & below), S{}) : 0.f;
                     cur[r] += n0 + __popcll(m1);
                 }
+                // Staging is slot-major: entry j (dealt to slot j mod TS) sits at
+                // (j mod TS) * 2G + j / TS, so each slot reads its entries from
+                // consecutive places (constant offsets within an unrolled step).
+                const int p0 = ((tl & (TS - 1)) << (g_log2 + 1)) + (tl >> ts_log2);
+                const int p1 = (((TL + tl) & (TS - 1)) << (g_log2 + 1)) + ((TL + tl) >> ts_log2);
                 // the previous chunk's reads are done (program order in the wave)
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                s_w[ebase + tl] = (int)w0;
-                s_w[ebase + TL + tl] = (int)w1;
+                s_w[ebase + p0] = (int)w0;
+                s_w[ebase + p1] = (int)w1;
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    s_v[(ebase + tl) * RB + r] = v0[r];
-                    s_v[(ebase + TL + tl) * RB + r] = v1[r];
+                    s_v[(ebase + p0) * RB + r] = v0[r];
+                    s_v[(ebase + p1) * RB + r] = v1[r];
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
                 const int cnt = min(CH, u1 - base);
-                const int nvalid = (cnt - slot + (1 << ts_log2) - 1) >> ts_log2;  // this slot's
+                const int nvalid = (cnt - slot + TS - 1) >> ts_log2;  // this slot's entries
+                const int* sw = s_w + ebase + (slot << (g_log2 + 1));
+                const float* sv = s_v + (ebase + (slot << (g_log2 + 1))) * RB;
                 for (int k = 0; k < nvalid; k += U) {
                     uint32_t w[U];
                     float v[U][RB];
                     float bv[U][VEC];
+                    if (col_ok && k + U <= nvalid) {
+                        // a whole step of this slot's entries: no per-entry checks
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int e = ((k + u) << ts_log2) + slot;
-                        const bool ok = k + u < nvalid;
-                        w[u] = ok ? (uint32_t)s_w[ebase + e] : 0u;
-                        if (ok) {
-                            read_vals<RB>(s_v + (ebase + e) * RB, v[u]);
-                        } else {
-#pragma unroll
-                            for (int r = 0; r < RB; ++r) v[u][r] = 0.f;
-                        }
-                        if (ok && col_ok) {
+                        for (int u = 0; u < U; ++u) {
+                            w[u] = (uint32_t)sw[k + u];
                             load_row<S, VEC>(b_row(w[u] & kColMask), bv[u]);
-                        } else {
+                        }
 #pragma unroll
-                            for (int e2 = 0; e2 < VEC; ++e2) bv[u][e2] = 0.f;
+                        for (int u = 0; u < U; ++u) read_vals<RB>(sv + (k + u) * RB, v[u]);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const bool ok = k + u < nvalid;
+                            w[u] = ok ? (uint32_t)sw[k + u] : 0u;
+                            if (ok) {
+                                read_vals<RB>(sv + (k + u) * RB, v[u]);
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < RB; ++r) v[u][r] = 0.f;
+                            }
+                            if (ok && col_ok) {
+                                load_row<S, VEC>(b_row(w[u] & kColMask), bv[u]);
+                            } else {
+#pragma unroll
+                                for (int e2 = 0; e2 < VEC; ++e2) bv[u][e2] = 0.f;
+                            }
                         }
                     }
 #pragma unroll
