@@ -245,7 +245,7 @@ int spmm_plan_destroy(spmm_plan_t plan);
  * A in increasing order within each row of A^T, and perm[nnz] with
  * AT_vals[q] = A_vals[perm[q]]. Stored in the plan; allocates; synchronises.
  * The product with A^T gets a plan of its own, made with the plan's mode
- * (RULE for a plan made from a forced config). */
+ * (RULE for a plan made from a forced config or in mode ROWBLOCK). */
 int spmm_transpose_build(spmm_plan_t plan, void* stream);
 
 /* Copy the transpose into caller buffers (device pointers: k + 1, nnz, nnz

@@ -66,8 +66,9 @@ int spmm_transpose_build(spmm_plan_t plan, void* stream) {
         return hip_fail(e, "transpose build");
     }
     // The product with A^T runs in float32 (values are widened at gather),
-    // planned by the plan's own mode (the MI355X rule for a forced shape).
-    const int mode = p.mode >= 0 ? p.mode : SPMM_MODE_RULE;
+    // planned by the plan's own mode (the MI355X rule for a forced shape, and
+    // for a forced row-block plan, whose conditions A^T need not meet).
+    const int mode = p.mode >= 0 && p.mode != SPMM_MODE_ROWBLOCK ? p.mode : SPMM_MODE_RULE;
     spmm_plan_s* tp = nullptr;
     int rc = create_plan(&tp, tr.at_rowptr, tr.at_colind, p.k, p.m, p.nnz, p.n, p.ld, SPMM_F32,
                          mode, nullptr, st, false);

@@ -135,7 +135,7 @@ def test_scatter_transpose_free(kernel, n):
 
 
 @pytest.mark.parametrize("kernel,mode", [(RS, "paper"), (MG, "paper"), (NZ, "paper"),
-                                         (None, "nzsplit")])
+                                         (None, "nzsplit"), (None, "rowblock")])
 def test_backward_integer_exact(kernel, mode):
     """Integer data: dB and dvals bit for bit. With mode nzsplit the plan of
     A^T uses the nonzero split too; SDDMM walks diagonal pieces either way."""
