@@ -368,6 +368,59 @@ def _best_of(nv, rp, ci, m, k, nnz, n, vals, Bt, C, kernel):
     return best
 
 
+def rowblock_sweep():
+    """Row blocks against row split and the merge path on matrices whose
+    neighbouring rows share columns (2-D and 3-D stencils) and on controls
+    without that sharing (a banded matrix with random columns, the uniform
+    matrix), at n = 16, 32, 64, 128 in float32; each kernel at its fastest
+    shape. Prints one JSON line per (matrix, n) with the union size of blocks
+    of 4 rows relative to the entry count."""
+    import torch
+    from paper_1803_08601_amd import native as nv
+    from paper_1803_08601_amd import workloads as wl
+    mats = [("27-point 3-D 128^3", lambda: wl.grid_stencil(11, (128, 128, 128), 27)),
+            ("7-point 3-D 128^3", lambda: wl.grid_stencil(12, (128, 128, 128), 7)),
+            ("9-point 2-D 1448^2", lambda: wl.grid_stencil(13, (1448, 1448), 9)),
+            ("5-point 2-D 1448^2", lambda: wl.grid_stencil(14, (1448, 1448), 5)),
+            ("banded, 16 random in +-512, 2M rows", lambda: wl.banded(15, 2_097_152)),
+            ("uniform 16 per row, 2M x 2M", lambda: wl.plain(seed=16, m=2_097_152,
+                                                             k=2_097_152))]
+    rb_shapes = [dict(kernel=nv.SPMM_KERNEL_ROWBLOCK, rows_per_block=R, lanes_per_row=l, unroll=u)
+                 for R in (2, 4, 8) for l in (64, 32, 16, 8) for u in (2, 4)]
+    for desc, make in mats:
+        A = make()
+        rows = np.repeat(np.arange(A.m, dtype=np.int64) // 4, A.row_lengths())
+        ratio4 = np.unique(rows * A.k + A.colind).size / A.nnz
+        del rows
+        rp, ci = torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colind).cuda()
+        vals = torch.from_numpy(A.vals.astype(np.float32)).cuda()
+        for n in (16, 32, 64, 128):
+            Bt = torch.from_numpy(wl.dense(17, A.k, n)).cuda()
+            C = torch.empty(A.m, n, device="cuda")
+            rs = _best_of(nv, rp, ci, A.m, A.k, A.nnz, n, vals, Bt, C, "rowsplit")
+            mg = _best_of(nv, rp, ci, A.m, A.k, A.nnz, n, vals, Bt, C, "merge")
+            rb = None
+            for cfg in rb_shapes:
+                try:
+                    ms, _ = _plan_time(nv, rp, ci, A.m, A.k, A.nnz, n, vals, Bt, C, cfg=cfg,
+                                       steps=3)
+                except nv.SpmmError:
+                    continue
+                if rb is None or ms < rb[0]:
+                    rb = (ms, cfg)
+            best = min((rs[0], "rowsplit"), (mg[0], "merge"), (rb[0], "rowblock"))
+            rec = {"matrix": desc, "n": n, "m": A.m, "nnz": A.nnz,
+                   "union_ratio_4": round(ratio4, 3), "max_row": int(A.row_lengths().max()),
+                   "rowsplit_ms": round(rs[0], 4), "merge_ms": round(mg[0], 4),
+                   "rowblock_ms": round(rb[0], 4), "rowblock_shape": rb[1],
+                   "fastest": best[1]}
+            print(json.dumps(rec), flush=True)
+            del Bt, C
+            torch.cuda.empty_cache()
+        del rp, ci, vals, A
+        torch.cuda.empty_cache()
+
+
 def heuristic_sweep(n=64):
     """Both kernels on matrices whose mean row length spans the Sec. 5.4
     threshold: dense-as-CSR shapes from 2 x 8.4M to 8.4M x 2 (2^24 entries,
@@ -632,6 +685,8 @@ def main():
                     help="run just one extra measurement and print its JSON (for profiling)")
     ap.add_argument("--sweep", action="store_true",
                     help="kernel-choice sweep over mean row length (re-derives the Sec. 5.4 threshold)")
+    ap.add_argument("--rowblock-sweep", action="store_true",
+                    help="row blocks against row split and merge on stencils and controls")
     ap.add_argument("--nzsplit", action="store_true",
                     help="nonzero split against merge path and row split on matrices with "
                          "runs of empty rows")
@@ -670,6 +725,9 @@ def main():
         return
     if args.nzsplit:
         nz_compare(args.n)
+        return
+    if args.rowblock_sweep:
+        rowblock_sweep()
         return
     if args.table_size_sweep:
         table_size_sweep(args.n)

@@ -66,20 +66,24 @@ typedef enum spmm_dtype { SPMM_F32 = 0, SPMM_BF16 = 1, SPMM_F16 = 2 } spmm_dtype
  *   AUTOTUNE : time the candidate kernels and shapes on scratch buffers of
  *              the plan's sizes and keep the fastest.
  *   ROWSPLIT / MERGE : force that kernel with default shapes.
- *   RULE     : the O(1) rule re-derived on MI355X from the kernel-choice
+ *   RULE     : the rule re-derived on MI355X from the kernel-choice
  *              sweep (the Sec. 5.4 procedure on this GPU): merge-based when
  *              the mean row length is below 4 or the longest row has 4096
  *              or more entries (row split cannot spread one row over
- *              several workgroups), row split otherwise.
+ *              several workgroups); otherwise row blocks of 2 rows when
+ *              n >= 32, the rows are sorted, k < 2^24 and blocks of 2 rows
+ *              hold at most 0.9 distinct columns per entry (from the
+ *              row-block sweep; costs a row-order check and one union
+ *              count on the device); row split otherwise.
  *   NZSPLIT  : force the nonzero split (Sec. 4, scheme (a): the 1-D
  *              partition the paper's merge-based kernel implements) with
  *              default shapes.
- *   ROWBLOCK : force the row-block kernel (4 rows per block, default
+ *   ROWBLOCK : force the row-block kernel (2 rows per block, default
  *              shapes); SPMM_ERR_UNSUPPORTED unless every row's column
  *              indices strictly increase and k < 2^24. AUTOTUNE also times
- *              it when those hold, the longest row has at most 4096 entries
- *              and blocks of 4 rows hold at most 85 % as many distinct
- *              columns as entries. */
+ *              it (2 and 4 rows per block) when those hold, the longest row
+ *              has at most 4096 entries and blocks of 2 rows hold at most
+ *              0.9 distinct columns per entry. */
 typedef enum spmm_mode {
     SPMM_MODE_PAPER = 0,
     SPMM_MODE_AUTOTUNE = 1,
@@ -134,7 +138,7 @@ typedef struct spmm_config {
                               vec; the product runs over ceil(n / tile_cols) tiles, each
                               re-reading A but touching only its columns of B. 0 = as wide as
                               one wavefront covers (64 * vec columns) */
-    int32_t rows_per_block;/* ROWBLOCK: rows per block, 2, 4 or 8 (0 = 4); other kernels
+    int32_t rows_per_block;/* ROWBLOCK: rows per block, 2, 4 or 8 (0 = 2); other kernels
                               ignore it */
 } spmm_config;
 

@@ -222,6 +222,11 @@ static int prepare_rowblock(const spmm_plan_s& p, RowBlocks& rb, int R, hipStrea
     return SPMM_OK;
 }
 
+// Distinct columns per entry of blocks of 2 rows at or below which row blocks
+// are worth trying (mode RULE also needs n >= kRuleMinN).
+constexpr double kRuleUnionRatio = 0.9;
+constexpr int64_t kRuleMinN = 32;
+
 static int check_config(const spmm_plan_s& p, spmm_config& c) {
     const int v16 = vec16(p.dtype);
     const bool can16 = (p.n % v16 == 0) && (p.ld % v16 == 0);
@@ -229,7 +234,7 @@ static int check_config(const spmm_plan_s& p, spmm_config& c) {
         c.kernel != SPMM_KERNEL_NZSPLIT && c.kernel != SPMM_KERNEL_ROWBLOCK)
         return fail(SPMM_ERR_INVALID, "config.kernel %d is not a kernel", c.kernel);
     if (c.kernel == SPMM_KERNEL_ROWBLOCK) {
-        if (c.rows_per_block == 0) c.rows_per_block = 4;
+        if (c.rows_per_block == 0) c.rows_per_block = 2;
         if (c.rows_per_block != 2 && c.rows_per_block != 4 && c.rows_per_block != 8)
             return fail(SPMM_ERR_UNSUPPORTED, "config.rows_per_block %d: use 2, 4 or 8",
                         c.rows_per_block);
@@ -256,7 +261,10 @@ static int check_config(const spmm_plan_s& p, spmm_config& c) {
     if (c.unroll == 0) c.unroll = 4;
     if (c.unroll != 1 && c.unroll != 2 && c.unroll != 4 && c.unroll != 8)
         return fail(SPMM_ERR_UNSUPPORTED, "config.unroll %d: use 1, 2, 4 or 8", c.unroll);
-    if (c.lanes_per_row == 0) {
+    if (c.lanes_per_row == 0 && c.kernel == SPMM_KERNEL_ROWBLOCK) {
+        // one slot per block: the fastest in the row-block sweep from n = 64 on
+        c.lanes_per_row = g;
+    } else if (c.lanes_per_row == 0) {
         // about four entries of an average row per slot
         const double d = p.m ? double(p.nnz) / double(p.m) : 0.0;
         int ts = 1;
@@ -345,7 +353,7 @@ static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_
     // Row blocks last: chosen only when faster than every kernel of the paper
     // by more than the tie margin.
     if (rowblock)
-        for (int R : {4, 8})
+        for (int R : {2, 4})
             for (int tc : tiles) {
                 int g_log2, nt;
                 slot_geometry(p.n, vec, &g_log2, &nt, tc);
@@ -397,7 +405,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     const void* use_B = own ? opts->B : nullptr;
     float* use_C = own ? opts->C : nullptr;
     MergeWs ws;
-    RowBlocks rb4, rb8;  // row-block structures of the candidates
+    RowBlocks rb2, rb4;  // row-block structures of the candidates
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SPMM_OK;
     auto cleanup = [&]() {
@@ -405,8 +413,8 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
         if (B) (void)hipFree(B);
         if (C) (void)hipFree(C);
         free_ws(ws);
+        free_rb(rb2);
         free_rb(rb4);
-        free_rb(rb8);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
@@ -433,7 +441,8 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     TUNE_HIP(hipEventCreate(&e1));
 
     // The row-block kernel is a candidate for sorted rows of moderate length
-    // whose blocks of 4 rows share enough columns to save gathers.
+    // whose blocks of 2 rows share enough columns to save gathers (the same
+    // test as mode RULE, without its bound on n).
     bool rowblock = (!opts || opts->rowblock) && p.nnz > 0 &&
                     p.k < (int64_t(1) << spmmk::kRowBlockColBits) && p.max_row_len <= 4096;
     if (rowblock) {
@@ -442,10 +451,10 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
         rowblock = p.sorted == 1;
     }
     if (rowblock) {
-        rc = prepare_rowblock(p, rb4, 4, st);
+        rc = prepare_rowblock(p, rb2, 2, st);
         if (rc != SPMM_OK) { cleanup(); return rc; }
-        rowblock = double(rb4.U) <= 0.85 * double(p.nnz);
-        if (!rowblock) free_rb(rb4);
+        rowblock = double(rb2.U) <= kRuleUnionRatio * double(p.nnz);
+        if (!rowblock) free_rb(rb2);
     }
 
     // Candidates within kTie (1.5 %, above the run-to-run spread of the
@@ -468,7 +477,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
             q.ws = ws;
         }
         if (c.kernel == SPMM_KERNEL_ROWBLOCK) {
-            RowBlocks& rb = c.rows_per_block == 4 ? rb4 : rb8;
+            RowBlocks& rb = c.rows_per_block == 2 ? rb2 : rb4;
             rc = prepare_rowblock(p, rb, c.rows_per_block, st);
             if (rc != SPMM_OK) { cleanup(); return rc; }
             q.rb = rb;
@@ -506,7 +515,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     }
     if (best_cfg.kernel == SPMM_KERNEL_ROWBLOCK && best_ms < 1e30) {
         // hand the chosen structure to the plan
-        RowBlocks& rb = best_cfg.rows_per_block == 4 ? rb4 : rb8;
+        RowBlocks& rb = best_cfg.rows_per_block == 2 ? rb2 : rb4;
         free_rb(p.rb);
         p.rb = rb;
         rb = RowBlocks{};
@@ -547,6 +556,25 @@ static int rule_choice(const spmm_plan_s& p) {
     const bool short_rows = p.nnz < 4 * p.m;
     const bool long_row = p.max_row_len >= 4096;
     return short_rows || long_row ? SPMM_KERNEL_MERGE : SPMM_KERNEL_ROWSPLIT;
+}
+
+// Row blocks in mode RULE (from the row-block sweep on MI355X): for a matrix
+// row split would take, when n >= 32, the rows are sorted, k < 2^24 and blocks
+// of 2 rows hold at most 0.9 distinct columns per entry. Builds the
+// structure for blocks of 2 rows, kept when chosen.
+
+static int rule_rowblock(spmm_plan_s& p, hipStream_t st, bool* chosen) {
+    *chosen = false;
+    if (p.n < kRuleMinN || p.nnz == 0 || p.k >= (int64_t(1) << spmmk::kRowBlockColBits) ||
+        p.max_row_len > 4096)
+        return SPMM_OK;
+    int rc = ensure_sorted(p, st);
+    if (rc != SPMM_OK || p.sorted != 1) return rc;
+    rc = prepare_rowblock(p, p.rb, 2, st);
+    if (rc != SPMM_OK) return rc;
+    *chosen = double(p.rb.U) <= kRuleUnionRatio * double(p.nnz);
+    if (!*chosen) free_rb(p.rb);
+    return SPMM_OK;
 }
 
 static int check_dims(int64_t m, int64_t k, int64_t nnz, int64_t n, int64_t ld) {
@@ -615,14 +643,19 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
         } else if (mode == SPMM_MODE_AUTOTUNE) {
             rc = autotune(*p, st, opts);
         } else {
-            const int kern = mode == SPMM_MODE_PAPER     ? p->paper_choice
-                             : mode == SPMM_MODE_RULE    ? rule_choice(*p)
-                             : mode == SPMM_MODE_MERGE   ? SPMM_KERNEL_MERGE
-                             : mode == SPMM_MODE_NZSPLIT ? SPMM_KERNEL_NZSPLIT
-                             : mode == SPMM_MODE_ROWBLOCK ? SPMM_KERNEL_ROWBLOCK
-                                                          : SPMM_KERNEL_ROWSPLIT;
+            int kern = mode == SPMM_MODE_PAPER     ? p->paper_choice
+                       : mode == SPMM_MODE_RULE    ? rule_choice(*p)
+                       : mode == SPMM_MODE_MERGE   ? SPMM_KERNEL_MERGE
+                       : mode == SPMM_MODE_NZSPLIT ? SPMM_KERNEL_NZSPLIT
+                       : mode == SPMM_MODE_ROWBLOCK ? SPMM_KERNEL_ROWBLOCK
+                                                    : SPMM_KERNEL_ROWSPLIT;
+            if (mode == SPMM_MODE_RULE && kern == SPMM_KERNEL_ROWSPLIT && (!opts || opts->rowblock)) {
+                bool rb = false;
+                rc = rule_rowblock(*p, st, &rb);
+                if (rb) kern = SPMM_KERNEL_ROWBLOCK;
+            }
             p->cfg = spmm_config{kern, 0, 0, opts ? opts->fixed_unroll : 0, 0, 0};
-            rc = check_config(*p, p->cfg);
+            if (rc == SPMM_OK) rc = check_config(*p, p->cfg);
         }
     }
     if (rc == SPMM_OK && opts && opts->max_W && p->cfg.items_per_wg > opts->max_W)

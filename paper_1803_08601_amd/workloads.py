@@ -191,6 +191,62 @@ def stencil27(seed=1003, g=128, values="stencil") -> CSR:
     return CSR(rowptr_from_lengths(lengths), colind, vals, m, m)
 
 
+def grid_stencil(seed, dims, points, values="uniform") -> CSR:
+    """Stencil matrix on a grid of the given dimensions (row index x + g0*y +
+    g0*g1*z ...), no wrap at the boundary: `points` = 3^d takes every offset
+    in {-1, 0, 1}^d (the 9- and 27-point stencils), `points` = 2d + 1 the
+    axis neighbours only (the 5- and 7-point stencils). Columns ascend within
+    each row."""
+    import itertools
+    rng = _rng(seed, 0)
+    d = len(dims)
+    m = int(np.prod(dims))
+    idx = np.arange(m, dtype=np.int64)
+    coord, stride, rem = [], [], idx
+    s = 1
+    for g in dims:
+        coord.append(rem % g)
+        rem = rem // g
+        stride.append(s)
+        s *= g
+    if points == 3 ** d:
+        offs = list(itertools.product((-1, 0, 1), repeat=d))
+    elif points == 2 * d + 1:
+        offs = [tuple(0 for _ in range(d))]
+        for a in range(d):
+            for sgn in (-1, 1):
+                offs.append(tuple(sgn if b == a else 0 for b in range(d)))
+    else:
+        raise ValueError("points must be 3^d or 2d + 1")
+    offs.sort(key=lambda o: sum(o[a] * stride[a] for a in range(d)))  # ascending columns
+    cols = np.empty((m, len(offs)), dtype=np.int32)
+    ok = np.ones((m, len(offs)), dtype=bool)
+    for t, o in enumerate(offs):
+        c = idx.copy()
+        for a in range(d):
+            ok[:, t] &= (coord[a] + o[a] >= 0) & (coord[a] + o[a] < dims[a])
+            c += o[a] * stride[a]
+        cols[:, t] = c.astype(np.int32)
+    lengths = ok.sum(axis=1)
+    colind = cols[ok]
+    return CSR(rowptr_from_lengths(lengths), colind, _values(rng, colind.shape[0], values), m, m)
+
+
+def banded(seed, m, per_row=16, half_band=512, values="uniform") -> CSR:
+    """Each row holds `per_row` distinct random columns in a window of
+    2 * half_band + 1 columns around its diagonal (shifted inward at the
+    edges), ascending."""
+    rng = _rng(seed, 0)
+    width = 2 * half_band + 1
+    if m < width:
+        raise ValueError("m must be at least 2 * half_band + 1")
+    lengths = np.full(m, per_row, dtype=np.int64)
+    rel = distinct_sorted_columns(rng, lengths, width).astype(np.int64)
+    lo = np.clip(np.arange(m, dtype=np.int64) - half_band, 0, m - width)
+    colind = (np.repeat(lo, per_row) + rel).astype(np.int32)
+    return CSR(rowptr_from_lengths(lengths), colind, _values(rng, colind.shape[0], values), m, m)
+
+
 def chung_lu_graph(seed=1004, N=500_000, mean_deg=32.0, cap=100_000):
     """Undirected simple graph with power-law expected degrees: node weights
     from the same Pareto law as ``power_law`` (exponent 2.1), endpoints drawn

@@ -90,7 +90,7 @@ def test_power_law_modes(mode):
         if mode == "nzsplit":
             assert info.config.kernel == NZ
         if mode == "rowblock":
-            assert info.config.kernel == RB and info.config.rows_per_block == 4
+            assert info.config.kernel == RB and info.config.rows_per_block == 2
 
 
 @pytest.mark.parametrize("mode", ["rowsplit", "merge", "nzsplit", "rowblock", "autotune"])
@@ -493,13 +493,25 @@ def test_plan_methods_refuse_bad_tensors():
 
 def test_rule_mode_choice():
     """The MI355X rule: merge-based for power-law rows (a row of >= 4096
-    entries) or a mean below 4, row split for regular rows."""
-    cases = [(wl.power_law(seed=51, m=40_000, cap=20_000), nv.SPMM_KERNEL_MERGE),
-             (wl.stencil27(g=20), nv.SPMM_KERNEL_ROWSPLIT),
-             (wl.plain(m=2000, k=2000), nv.SPMM_KERNEL_ROWSPLIT),
-             (wl.random_csr(8, 5000, 4000, density=0.0005), nv.SPMM_KERNEL_MERGE)]
-    for A, want in cases:
-        B = wl.dense(5, A.k, 16)
-        C, plan = run(A, dev(A.vals), dev(B), 16, mode="rule")
-        assert plan.info().config.kernel == want
-        check(A, dev(A.vals), dev(B), 16, C)
+    entries) or a mean below 4; row blocks of 2 rows for sorted rows whose
+    pairs share columns (at most 0.9 distinct columns per entry) when
+    n >= 32; row split otherwise."""
+    S = wl.stencil27(g=20)
+    ci = S.colind.copy()
+    ci[S.rowptr[5]:S.rowptr[6]] = ci[S.rowptr[5]:S.rowptr[6]][::-1]  # one row out of order
+    S_unsorted = wl.CSR(S.rowptr, ci, S.vals, S.m, S.k)
+    cases = [(wl.power_law(seed=51, m=40_000, cap=20_000), 16, MG),
+             (S, 16, RS),
+             (S, 64, RB),
+             (wl.grid_stencil(3, (300, 300), 5), 32, RB),
+             (S_unsorted, 64, RS),
+             (wl.plain(m=2000, k=2000), 64, RS),
+             (wl.random_csr(8, 5000, 4000, density=0.0005), 64, MG)]
+    for A, n, want in cases:
+        B = wl.dense(5, A.k, n)
+        C, plan = run(A, dev(A.vals), dev(B), n, mode="rule")
+        info = plan.info()
+        assert info.config.kernel == want, (A.m, n)
+        if want == RB:
+            assert info.config.rows_per_block == 2
+        check(A, dev(A.vals), dev(B), n, C)

@@ -77,3 +77,23 @@ def test_batch_specs():
     _check_csr(Q)
     L = Q.row_lengths()
     assert L.min() >= 8 and L.max() <= 64
+
+
+def test_grid_stencils_and_banded():
+    # 7-point on 4^3: corners 4, edges 5, faces 6, interior 7 neighbours
+    A = wl.grid_stencil(1, (4, 4, 4), 7)
+    assert np.array_equal(np.bincount(A.row_lengths()), [0, 0, 0, 0, 8, 24, 24, 8])
+    # the 27-point form has the structure of stencil27
+    B, S = wl.grid_stencil(1, (6, 6, 6), 27), wl.stencil27(g=6)
+    assert np.array_equal(B.rowptr, S.rowptr) and np.array_equal(B.colind, S.colind)
+    # 5-point on a 5 x 5 grid: 4 * 5 * 4 horizontal and vertical neighbour pairs
+    C = wl.grid_stencil(1, (5, 5), 5)
+    assert C.nnz == 25 + 2 * 2 * 5 * 4
+    D = wl.banded(2, 3000, per_row=16, half_band=100)
+    assert np.all(D.row_lengths() == 16)
+    rows = np.repeat(np.arange(D.m), 16)
+    lo = np.clip(rows - 100, 0, D.m - 201)
+    assert np.all((D.colind >= lo) & (D.colind <= lo + 200))
+    for M in (A, C, D):
+        for i in range(0, M.m, max(1, M.m // 50)):
+            assert np.all(np.diff(M.colind[M.rowptr[i]:M.rowptr[i + 1]]) > 0)
