@@ -354,6 +354,9 @@ def _best_of(nv, rp, ci, m, k, nnz, n, vals, Bt, C, kernel):
         code = nv.SPMM_KERNEL_MERGE if kernel == "merge" else nv.SPMM_KERNEL_NZSPLIT
         shapes = [dict(kernel=code, items_per_wg=W, unroll=u) for W in (1024, 2048, 4096)
                   for u in (2, 4, 8)]
+    elif kernel == "rowblock":
+        shapes = [dict(kernel=nv.SPMM_KERNEL_ROWBLOCK, rows_per_block=R, lanes_per_row=l,
+                       unroll=u) for R in (2, 4) for l in (0, 64, 32, 16) for u in (2, 4)]
     else:
         shapes = [dict(kernel=0, lanes_per_row=l, unroll=u) for l in (0, 64, 32, 16, 8)
                   for u in (2, 4, 8)]
@@ -446,6 +449,7 @@ def heuristic_sweep(n=64):
             ci = torch.arange(L, dtype=torch.int32, device="cuda").repeat(m)
             k, nnz, desc = L, m * L, f"dense {m} x {L}"
             maxrow = L
+            r2 = 0.5  # every pair of rows holds the same columns
         else:
             shape, mean = a, b
             rng = np.random.default_rng(int(shape * 100 + mean))
@@ -455,6 +459,9 @@ def heuristic_sweep(n=64):
             ci = torch.from_numpy(cols).cuda()
             m, k, nnz = 1_000_000, 1_000_000, int(lengths.sum())
             maxrow = int(lengths.max())
+            pair = np.repeat(np.arange(m, dtype=np.int64) // 2, lengths)
+            r2 = np.unique(pair * k + cols).size / nnz
+            del pair
             desc = f"power law, tail exponent {shape + 1.0:.1f}, mean {mean:g}, 1M x 1M"
         g = torch.Generator(device="cuda")
         g.manual_seed(7)
@@ -463,13 +470,27 @@ def heuristic_sweep(n=64):
         C = torch.empty(m, n, device="cuda")
         rs = _best_of(nv, rp, ci, m, k, nnz, n, vals, Bt, C, "rowsplit")
         mg = _best_of(nv, rp, ci, m, k, nnz, n, vals, Bt, C, "merge")
+        # row blocks only where the rule could take them (rows of at most 4096)
+        rb = _best_of(nv, rp, ci, m, k, nnz, n, vals, Bt, C, "rowblock") if maxrow <= 4096 \
+            else None
         d = nnz / m
+        if nnz < 4 * m or maxrow >= 4096:
+            rule = "merge"
+        elif n >= 32 and r2 <= 0.9:
+            rule = "rowblock"
+        else:
+            rule = "rowsplit"
+        times = {"rowsplit": rs[0], "merge": mg[0], "rowblock": rb[0] if rb else float("inf")}
         rec = {"matrix": desc, "m": m, "k": k, "nnz": nnz, "mean_row": d, "max_row": maxrow,
+               "r2": round(r2, 3),
                "rowsplit_ms": round(rs[0], 4), "merge_ms": round(mg[0], 4),
+               "rowblock_ms": round(rb[0], 4) if rb else None,
                "rowsplit_shape": rs[1], "merge_shape": mg[1],
+               "rowblock_shape": rb[1] if rb else None,
                "faster": "merge" if mg[0] < rs[0] else "rowsplit",
+               "fastest_of_three": min(times, key=times.get),
                "paper_rule": "merge" if 100 * nnz < 935 * m else "rowsplit",
-               "mi355x_rule": "merge" if (nnz < 4 * m or maxrow >= 4096) else "rowsplit"}
+               "mi355x_rule": rule}
         print(json.dumps(rec), flush=True)
         recs.append(rec)
         del rp, ci, vals, Bt, C
@@ -488,13 +509,18 @@ def heuristic_sweep(n=64):
             tot += np.log(pick / min(r["merge_ms"], r["rowsplit_ms"]))
         return float(np.exp(tot / len(recs)))
     def rule_stats(key):
-        ok = [r[key] == r["faster"] for r in recs]
-        tot = sum(np.log((r["merge_ms"] if r[key] == "merge" else r["rowsplit_ms"])
-                         / min(r["merge_ms"], r["rowsplit_ms"])) for r in recs)
+        # against the fastest of the three kernels
+        def t(r, kern):
+            return r[kern + "_ms"] if r[kern + "_ms"] is not None else float("inf")
+        ok = [r[key] == r["fastest_of_three"] for r in recs]
+        tot = sum(np.log(t(r, r[key]) / min(t(r, q) for q in ("rowsplit", "merge", "rowblock")))
+                  for r in recs)
         return round(sum(ok) / len(ok), 3), round(float(np.exp(tot / len(recs))), 3)
     mi_acc, mi_loss = rule_stats("mi355x_rule")
     print(json.dumps({"summary": "heuristic sweep", "n": n, "matrices": len(recs),
-                      "mi355x_rule": "merge if mean < 4 or longest row >= 4096",
+                      "mi355x_rule": "merge if mean < 4 or longest row >= 4096; else row blocks "
+                                     "of 2 if n >= 32 and pairs of rows hold <= 0.9 distinct "
+                                     "columns per entry; else row split",
                       "mi355x_rule_accuracy": mi_acc, "mi355x_rule_geomean_slowdown": mi_loss,
                       "paper_threshold": 9.35, "paper_rule_accuracy": round(acc(9.35), 3),
                       "paper_rule_geomean_slowdown": round(loss(9.35), 3),
