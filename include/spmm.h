@@ -166,8 +166,9 @@ typedef struct spmm_batch_s* spmm_batch_t;
  * several host threads; on a miss it reads
  * A_rowptr[m] back to the host (one 4-byte copy and a stream sync, so this
  * call is not capture-safe on a miss) and plans in RULE mode (the Sec. 5.4
- * procedure re-derived on MI355X; create a plan with SPMM_MODE_PAPER for the
- * paper's own threshold). The structure
+ * procedure re-derived on MI355X, whose row statistics, row-order check and
+ * union count also synchronise the stream; create a plan with
+ * SPMM_MODE_PAPER for the paper's own threshold). The structure
  * behind a cached (A_rowptr, A_colind) pair must not change; call
  * spmm_cache_clear() after changing it. Returns SPMM_OK for m == 0 or n == 0
  * without touching memory. */
