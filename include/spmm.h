@@ -27,6 +27,9 @@
  * and never synchronise the host, so they may be captured into a hipGraph.
  * Create/build calls may allocate and synchronise.
  *
+ * Sizes: m, k, n and ld fit int32; nnz is at most 2^31 - 4097 (entry
+ * indices are int32 in the kernels); larger sizes give SPMM_ERR_UNSUPPORTED.
+ *
  * Errors: every call returns an int status (spmm_status). Nothing aborts or
  * throws across the ABI. spmm_last_error() returns a thread-local message
  * for the last failing call on this thread. Argument checks happen on the
@@ -140,6 +143,19 @@ typedef struct spmm_config {
                               one wavefront covers (64 * vec columns) */
     int32_t rows_per_block;/* ROWBLOCK: rows per block, 2, 4 or 8 (0 = 2); other kernels
                               ignore it */
+    int32_t tile_order;    /* ROWSPLIT / ROWBLOCK: order in which workgroups take their rows.
+                              0 = automatic: strips across planes (see below) when the plan
+                              finds plane structure and one plane of B rows is larger than an
+                              XCD's 4 MB L2, else row order; 1 = row order; 2 = strips across
+                              planes whenever plane structure is found. Plane structure: the
+                              offsets colind - row form a near cluster (|offset| <= h) and a
+                              far one around +-D no wider than it, with D >= 16 h - the
+                              neighbour planes of a 3-D stencil, D rows apart. Rows are then
+                              taken in strips of S consecutive rows (S a power of two dividing
+                              D, the largest whose B rows for three planes fill at most 2 MB)
+                              through every plane before the next strip, so each B row is
+                              reused from L2 by the three planes that need it. Only the order
+                              of the workgroups changes: results are bitwise the same. */
 } spmm_config;
 
 typedef struct spmm_plan_info {
@@ -155,26 +171,59 @@ typedef struct spmm_plan_info {
     double mean_row_len;   /* nnz / m */
     double tuned_ms;       /* AUTOTUNE: median time of the chosen candidate, else 0 */
     int32_t has_transpose; /* spmm_transpose_build has run */
+    int64_t long_rows;     /* rows with 1024 or more entries (device row statistics) */
+    int64_t plane_rows;    /* row split / row blocks taken in strips: the plane distance D in
+                              rows, else 0 */
+    int64_t strip_rows;    /* ... and the strip S in rows, else 0 */
 } spmm_plan_info;
 
 typedef struct spmm_plan_s* spmm_plan_t;
 typedef struct spmm_batch_s* spmm_batch_t;
 
 /* ---------------------------------------------------------------- one call
- * C = A * B in float32 (Sec. 1). Uses an internal plan cache keyed by
- * (A_rowptr, A_colind, m, k, n, ld, device, stream), safe to call from
- * several host threads; on a miss it reads
- * A_rowptr[m] back to the host (one 4-byte copy and a stream sync, so this
- * call is not capture-safe on a miss) and plans in RULE mode (the Sec. 5.4
- * procedure re-derived on MI355X, whose row statistics, row-order check and
- * union count also synchronise the stream; create a plan with
- * SPMM_MODE_PAPER for the paper's own threshold). The structure
- * behind a cached (A_rowptr, A_colind) pair must not change; call
- * spmm_cache_clear() after changing it. Returns SPMM_OK for m == 0 or n == 0
- * without touching memory. */
+ * C = A * B in float32 (Sec. 1), with an internal plan cache keyed by
+ * (A_rowptr, A_colind, m, k, n, ld, device, stream); safe to call from
+ * several host threads.
+ *
+ * Kernel choice: mode RULE restricted to the paper's two kernels - the
+ * procedure of Sec. 5.4 (a threshold on row statistics, fitted by timing
+ * both kernels) re-derived on MI355X: merge-based when the mean row length
+ * is below 4 or the longest row has 4096 or more entries, row split
+ * otherwise. This departs from the paper's own threshold (merge-based iff
+ * nnz / m < 9.35; SPMM_MODE_PAPER of spmm_plan_create), which picks row
+ * split for every matrix with mean row length >= 9.35 however long its
+ * longest row - on a 1M x 1M power-law matrix with mean 16 and rows of up to
+ * 100,000 entries, 6x slower than merge-based. Row blocks are not used here.
+ *
+ * Synchronisation: on a miss the call reads A_rowptr[m] (nnz) and the device
+ * row statistics back to the host together - one stream synchronisation, so
+ * a miss is not capture-safe - then plans without further synchronisation.
+ * A hit only enqueues work.
+ *
+ * Structure changes: a cached row-split plan depends on the structure only
+ * through m. A cached merge-based plan keeps the merge-path partition of the
+ * row offsets it was made for, so each call first re-checks that partition
+ * against A_rowptr on the device (one small kernel): coordinates that no
+ * longer lie on the merge path of the current row offsets are searched
+ * again, so a different structure with the same nnz (for instance a new
+ * matrix placed at a freed matrix's addresses) is computed correctly. If
+ * A_rowptr[m] differs from the cached nnz, that call writes NaN into all of
+ * C and reads nothing else of A, and the next call with the same arguments
+ * returns SPMM_ERR_STATE and drops the plan (the one after plans afresh);
+ * call spmm_cache_clear() after freeing or changing a structure to avoid
+ * this. Rows with invalid offsets (A_rowptr[0] != 0, decreasing) are refused
+ * with SPMM_ERR_INVALID on a miss.
+ *
+ * Returns SPMM_OK for m == 0 or n == 0 without touching memory. */
 int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_vals,
              const float* B, float* C, int64_t m, int64_t k, int64_t n, int64_t ld,
              void* stream);
+
+/* Facts of the plan spmm_csr holds for these arguments (the same key; the
+ * current device): kernel, shape, row statistics. SPMM_ERR_STATE when no
+ * such plan is cached. */
+int spmm_csr_plan_info(const int32_t* A_rowptr, const int32_t* A_colind, int64_t m, int64_t k,
+                       int64_t n, int64_t ld, void* stream, spmm_plan_info* info_host);
 
 /* Drop every cached plan of spmm_csr (frees their workspace). */
 int spmm_cache_clear(void);

@@ -67,6 +67,12 @@ void slot_geometry(int64_t n, int vec, int* g_log2, int* col_tiles, int tile_col
     if (*col_tiles < 1) *col_tiles = 1;
 }
 
+// Tile order (spmm_config.tile_order): strips across planes when the plan
+// found plane structure and, in the automatic choice, one plane's B rows are
+// more than one XCD's L2 holds.
+constexpr int64_t kL2Bytes = int64_t(4) << 20;
+constexpr int64_t kStripBytes = int64_t(2) << 20;
+
 spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec) {
     spmmk::Shape s;
     s.vec = vec;
@@ -80,6 +86,14 @@ spmmk::Shape resolve_shape(const spmm_plan_s& p, int vec) {
     const int64_t row_bytes = p.ld * elem_bytes(p.dtype);
     s.short_addr = p.k < (int64_t(1) << 24) && row_bytes < (int64_t(1) << 24) &&
                    p.k * row_bytes <= int64_t(0xffffffff);
+    const bool rows = p.cfg.kernel == SPMM_KERNEL_ROWSPLIT || p.cfg.kernel == SPMM_KERNEL_ROWBLOCK;
+    const bool use = p.found_strip > 0 &&
+                     (p.cfg.tile_order == 2 ||
+                      (p.cfg.tile_order == 0 && p.found_plane * row_bytes > kL2Bytes));
+    if (rows && use) {
+        s.plane_rows = p.found_plane;
+        s.strip_rows = p.found_strip;
+    }
     return s;
 }
 
@@ -222,6 +236,39 @@ static int prepare_rowblock(const spmm_plan_s& p, RowBlocks& rb, int R, hipStrea
     return SPMM_OK;
 }
 
+// Plane structure of A for the tile order: the offsets colind - row form a
+// near cluster (|offset| <= near) and a far one, from far_lo to hi, around
+// +-D = (far_lo + hi) / 2 and no wider than the near one, with D at least 16
+// times the near extent (a 3-D stencil: D = one grid plane). The strip S is
+// the largest power of two dividing D whose rows' B rows for three planes
+// take at most kStripBytes. Computed once per plan (two passes over colind
+// and one synchronisation).
+static int find_planes(spmm_plan_s& p, hipStream_t st) {
+    p.found_plane = p.found_strip = 0;
+    if (p.m == 0 || p.nnz == 0) return SPMM_OK;
+    int* d = nullptr;
+    int h[3] = {0, 0, INT32_MAX};
+    SPMM_HIP(hipMalloc(&d, sizeof h));
+    hipError_t e = hipMemcpyAsync(d, h, sizeof h, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = spmmk::launch_offset_stats(p.rowptr, p.colind, p.m, d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "offset statistics");
+    const int64_t hi = h[0], near = std::max(h[1], 1), far_lo = h[2];
+    if (far_lo == INT32_MAX || hi < 2) return SPMM_OK;
+    const int64_t D = (far_lo + hi) / 2;
+    if (hi - far_lo > 2 * near + 2 || D < 16 * near) return SPMM_OK;
+    const int64_t row_bytes = p.ld * elem_bytes(p.dtype);
+    int64_t S = 1;
+    while (S * 2 * 3 * row_bytes <= kStripBytes) S *= 2;
+    while (S > 1 && D % S) S /= 2;
+    if (S < 64 || S >= D) return SPMM_OK;
+    p.found_plane = D;
+    p.found_strip = S;
+    return SPMM_OK;
+}
+
 // Distinct columns per entry of blocks of 2 rows at or below which row blocks
 // are worth trying (mode RULE also needs n >= kRuleMinN).
 constexpr double kRuleUnionRatio = 0.9;
@@ -247,6 +294,8 @@ static int check_config(const spmm_plan_s& p, spmm_config& c) {
     } else {
         c.rows_per_block = 0;
     }
+    if (c.tile_order < 0 || c.tile_order > 2)
+        return fail(SPMM_ERR_INVALID, "config.tile_order %d: use 0, 1 or 2", c.tile_order);
     if (c.vec == 0) c.vec = can16 ? v16 : 1;
     if (c.vec != 1 && c.vec != v16)
         return fail(SPMM_ERR_UNSUPPORTED, "config.vec %d: use 1 or %d for this dtype", c.vec, v16);
@@ -577,13 +626,20 @@ static int rule_rowblock(spmm_plan_s& p, hipStream_t st, bool* chosen) {
     return SPMM_OK;
 }
 
-static int check_dims(int64_t m, int64_t k, int64_t nnz, int64_t n, int64_t ld) {
+// Largest nnz: entry indices are int32 in the kernels, and their chunk loops
+// step up to 4096 entries past an index below nnz without overflowing.
+constexpr int64_t kMaxNnz = (int64_t(1) << 31) - 1 - 4096;
+
+int check_dims(int64_t m, int64_t k, int64_t nnz, int64_t n, int64_t ld) {
     const int64_t lim = (int64_t(1) << 31) - 1;
     if (m < 0 || k < 0 || nnz < 0 || n < 0)
         return fail(SPMM_ERR_INVALID, "negative size (m=%lld k=%lld nnz=%lld n=%lld)",
                     (long long)m, (long long)k, (long long)nnz, (long long)n);
     if (m > lim || k > lim || nnz > lim || n > lim)
         return fail(SPMM_ERR_UNSUPPORTED, "sizes must fit int32");
+    if (nnz > kMaxNnz)
+        return fail(SPMM_ERR_UNSUPPORTED, "nnz = %lld: at most 2^31 - 4097 entries",
+                    (long long)nnz);
     if (ld < std::max<int64_t>(1, n))
         return fail(SPMM_ERR_INVALID, "ld=%lld must be >= max(1, n=%lld)", (long long)ld,
                     (long long)n);
@@ -602,6 +658,8 @@ void destroy_plan(spmm_plan_s* p) {
     if (p->tr.perm) (void)hipFree(p->tr.perm);
     if (p->tr.at_vals) (void)hipFree(p->tr.at_vals);
     if (p->tplan) destroy_plan(p->tplan);
+    if (p->guard_host) (void)hipHostFree(p->guard_host);
+    if (p->aux_dev) (void)hipFree(p->aux_dev);
     delete p;
 }
 
@@ -632,10 +690,24 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
 
-    rc = row_stats(*p, st);
+    if (opts && opts->known_stats) {
+        p->max_row_len = opts->max_row_len;
+        p->long_rows = opts->long_rows;
+    } else {
+        rc = row_stats(*p, st);
+    }
     const bool want_rowblock = forced ? forced->kernel == SPMM_KERNEL_ROWBLOCK
                                       : mode == SPMM_MODE_ROWBLOCK;
     if (rc == SPMM_OK && want_rowblock) rc = ensure_sorted(*p, st);
+    // plane structure for the tile order: looked for when B is larger than
+    // an L2 (the automatic order needs more than that) or the order is forced
+    if (rc == SPMM_OK && p->m > 0 && p->nnz > 0 &&
+        ((forced && forced->tile_order == 2) ||
+         p->k * p->ld * elem_bytes(p->dtype) > kL2Bytes) &&
+        !(forced && (forced->tile_order == 1 || forced->kernel == SPMM_KERNEL_MERGE ||
+                     forced->kernel == SPMM_KERNEL_NZSPLIT)) &&
+        !(opts && (opts->known_stats || opts->no_planes)))
+        rc = find_planes(*p, st);
     if (rc == SPMM_OK) {
         if (forced) {
             p->cfg = *forced;
@@ -667,9 +739,10 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
         rc = prepare_rowblock(*p, p->rb, p->cfg.rows_per_block, st);
     // SDDMM walks diagonal merge pieces (their row ends fit its LDS); other
     // plans get such a partition for it.
-    if (rc == SPMM_OK && p->cfg.kernel != SPMM_KERNEL_MERGE && p->m > 0 && p->nnz > 0)
+    if (rc == SPMM_OK && p->cfg.kernel != SPMM_KERNEL_MERGE && p->m > 0 && p->nnz > 0 &&
+        !(opts && opts->no_sddmm))
         rc = prepare_merge(*p, p->sddmm_ws, kSddmmW, false, st);
-    if (rc == SPMM_OK) {
+    if (rc == SPMM_OK && !(opts && opts->no_sync)) {
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = hip_fail(e, "plan synchronise");
     }
@@ -695,6 +768,97 @@ using PlanRef = std::shared_ptr<spmm_plan_s>;
 static std::map<CacheKey, PlanRef> g_cache;
 static std::vector<CacheKey> g_cache_order;  // least recently used first
 static constexpr size_t kCacheCap = 64;
+
+static void fill_info(const spmm_plan_s* plan, spmm_plan_info* info) {
+    memset(info, 0, sizeof *info);
+    info->m = plan->m; info->k = plan->k; info->nnz = plan->nnz; info->n = plan->n;
+    info->ld = plan->ld;
+    info->dtype = plan->dtype;
+    info->mode = plan->mode;
+    info->paper_choice = plan->paper_choice;
+    info->config = plan->cfg;
+    const spmmk::Shape s = resolve_shape(*plan, plan->cfg.vec);
+    info->lanes_per_slot = 1 << s.g_log2;
+    info->col_tiles = s.col_tiles;
+    info->num_parts = is_merge(plan->cfg.kernel) ? plan->ws.P : 0;
+    info->max_row_len = plan->max_row_len;
+    info->mean_row_len = plan->m ? double(plan->nnz) / double(plan->m) : 0.0;
+    info->tuned_ms = plan->tuned_ms;
+    info->has_transpose = plan->tr.at_rowptr != nullptr || (plan->k == 0 && plan->tplan);
+    info->long_rows = plan->long_rows;
+    info->plane_rows = s.plane_rows;
+    info->strip_rows = s.strip_rows;
+}
+
+// The one-call path plans in mode RULE over the paper's two kernels (row
+// blocks are left out: their plan-time column structure would have to be
+// kept in step with A_colind). A miss reads back nnz and the row statistics
+// together (one stream synchronisation). A cached row-split plan depends on
+// the structure only through m; a cached merge plan's partition depends on
+// the row offsets, so every call re-checks it on the device first (see
+// spmm.h for what happens when the structure changed).
+static int csr_create(const int32_t* A_rowptr, const int32_t* A_colind, int64_t m, int64_t k,
+                      int64_t n, int64_t ld, hipStream_t st, bool pointers_ok, PlanRef* out) {
+    int* aux = nullptr;
+    SPMM_HIP(hipMalloc(&aux, 4 * sizeof(int)));
+    int h[4] = {0, 0, 1, 0};
+    hipError_t e = hipMemcpyAsync(aux, h, 3 * sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = spmmk::launch_row_stats(A_rowptr, m, aux, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(aux + 3, A_rowptr + m, sizeof(int), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, aux, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(aux);
+        return hip_fail(e, "one-call structure read-back");
+    }
+    const int64_t nnz = h[3];
+    auto refuse = [&](int code, const char* msg) {
+        (void)hipFree(aux);
+        return fail(code, "%s", msg);
+    };
+    if (nnz < 0) return refuse(SPMM_ERR_INVALID, "A_rowptr[m] < 0");
+    if (!h[2]) return refuse(SPMM_ERR_INVALID, "A_rowptr[0] != 0 or A_rowptr decreases");
+    if (nnz > 0 && !pointers_ok)
+        return refuse(SPMM_ERR_INVALID, "A_colind, A_vals or B is NULL");
+    TuneOpts o;
+    o.rowblock = false;
+    o.known_stats = true;
+    o.max_row_len = h[0];
+    o.long_rows = h[1];
+    o.no_sddmm = true;
+    o.no_sync = true;
+    spmm_plan_s* fresh = nullptr;
+    int rc = create_plan(&fresh, A_rowptr, A_colind, m, k, nnz, n, ld, SPMM_F32, SPMM_MODE_RULE,
+                         nullptr, st, false, &o);
+    if (rc) {
+        (void)hipFree(aux);
+        return rc;
+    }
+    fresh->aux_dev = aux;
+    if (is_merge(fresh->cfg.kernel)) {
+        e = hipHostMalloc(reinterpret_cast<void**>(&fresh->guard_host), sizeof(int),
+                          hipHostMallocMapped);
+        if (e == hipSuccess) {
+            *fresh->guard_host = 0;
+            e = hipHostGetDevicePointer(reinterpret_cast<void**>(&fresh->guard_dev),
+                                        fresh->guard_host, 0);
+        }
+        if (e != hipSuccess) {
+            destroy_plan(fresh);
+            return hip_fail(e, "one-call guard word");
+        }
+    }
+    *out = PlanRef(fresh, destroy_plan);
+    return SPMM_OK;
+}
+
+static CacheKey csr_key(const int32_t* A_rowptr, const int32_t* A_colind, int64_t m, int64_t k,
+                        int64_t n, int64_t ld, int dev, void* stream) {
+    // keyed by stream too: a merge-based plan's workspace must not be shared
+    // by work on two streams
+    return CacheKey{A_rowptr, A_colind, m, k, n, ld, dev, stream};
+}
 
 }  // namespace spmmh
 
@@ -769,23 +933,10 @@ int spmm_execute_semiring(spmm_plan_t plan, int32_t semiring, const void* A_vals
 int spmm_plan_info_get(spmm_plan_t plan, spmm_plan_info* info) {
     if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
     if (!info) return fail(SPMM_ERR_INVALID, "info is NULL");
-    memset(info, 0, sizeof *info);
-    info->m = plan->m; info->k = plan->k; info->nnz = plan->nnz; info->n = plan->n;
-    info->ld = plan->ld;
-    info->dtype = plan->dtype;
-    info->mode = plan->mode;
-    info->paper_choice = plan->paper_choice;
-    info->config = plan->cfg;
-    const spmmk::Shape s = resolve_shape(*plan, plan->cfg.vec);
-    info->lanes_per_slot = 1 << s.g_log2;
-    info->col_tiles = s.col_tiles;
-    info->num_parts = is_merge(plan->cfg.kernel) ? plan->ws.P : 0;
-    info->max_row_len = plan->max_row_len;
-    info->mean_row_len = plan->m ? double(plan->nnz) / double(plan->m) : 0.0;
-    info->tuned_ms = plan->tuned_ms;
-    info->has_transpose = plan->tr.at_rowptr != nullptr || (plan->k == 0 && plan->tplan);
+    fill_info(plan, info);
     return SPMM_OK;
 }
+
 
 int spmm_plan_partition(spmm_plan_t plan, int32_t* coords_host, int64_t cap) {
     if (!plan_alive(plan)) return fail(SPMM_ERR_STATE, "plan is destroyed or not a plan");
@@ -821,9 +972,8 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
     hipStream_t st = static_cast<hipStream_t>(stream);
     int dev = 0;
     SPMM_HIP(hipGetDevice(&dev));
-    // keyed by stream too: a merge-based plan's carry-out workspace must not be
-    // shared by work on two streams
-    const CacheKey key{A_rowptr, A_colind, m, k, n, ld, dev, stream};
+    const CacheKey key = csr_key(A_rowptr, A_colind, m, k, n, ld, dev, stream);
+    const bool pointers_ok = A_colind && A_vals && B;
     PlanRef p;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -835,18 +985,27 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
             g_cache_order.push_back(key);
         }
     }
+    if (p && p->guard_host && __atomic_load_n(p->guard_host, __ATOMIC_ACQUIRE)) {
+        // an earlier call found A_rowptr[m] != the plan's nnz: drop the plan
+        const long long old_nnz = (long long)p->nnz;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            auto it = g_cache.find(key);
+            if (it != g_cache.end() && it->second == p) {
+                g_cache.erase(it);
+                auto pos = std::find(g_cache_order.begin(), g_cache_order.end(), key);
+                if (pos != g_cache_order.end()) g_cache_order.erase(pos);
+            }
+        }
+        return fail(SPMM_ERR_STATE,
+                    "the CSR structure at these pointers changed: A_rowptr[m] is no longer the "
+                    "nnz (%lld) its cached plan was made for, and an earlier call filled its C "
+                    "with NaN; the plan is dropped and the next call plans afresh",
+                    old_nnz);
+    }
     if (!p) {
-        int32_t nnz32 = 0;
-        SPMM_HIP(hipMemcpyAsync(&nnz32, A_rowptr + m, sizeof nnz32, hipMemcpyDeviceToHost, st));
-        SPMM_HIP(hipStreamSynchronize(st));
-        if (nnz32 < 0) return fail(SPMM_ERR_INVALID, "A_rowptr[m] < 0");
-        if (nnz32 > 0 && (!A_colind || !A_vals || !B))
-            return fail(SPMM_ERR_INVALID, "A_colind, A_vals or B is NULL");
-        spmm_plan_s* fresh = nullptr;
-        rc = create_plan(&fresh, A_rowptr, A_colind, m, k, nnz32, n, ld, SPMM_F32, SPMM_MODE_RULE,
-                         nullptr, st, false);
+        rc = csr_create(A_rowptr, A_colind, m, k, n, ld, st, pointers_ok, &p);
         if (rc) return rc;
-        p = PlanRef(fresh, destroy_plan);
         std::vector<PlanRef> evict;  // released after the lock
         {
             std::lock_guard<std::mutex> lk(g_mu);
@@ -864,10 +1023,32 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
                 g_cache_order.erase(g_cache_order.begin());
             }
         }
-    } else if (p->nnz > 0 && (!A_colind || !A_vals || !B)) {
+    } else if (p->nnz > 0 && !pointers_ok) {
         return fail(SPMM_ERR_INVALID, "A_colind, A_vals or B is NULL");
     }
+    if (p->guard_dev && is_merge(p->cfg.kernel)) {
+        const hipError_t e = spmmk::launch_merge_revalidate(
+            A_rowptr, m, p->nnz, p->cfg.items_per_wg, p->ws.P, p->ws.coords, C, n, ld,
+            p->guard_dev, st);
+        if (e != hipSuccess) return hip_fail(e, "partition re-check launch");
+    }
     return forward(*p, A_rowptr, A_colind, A_vals, B, C, st);
+}
+
+int spmm_csr_plan_info(const int32_t* A_rowptr, const int32_t* A_colind, int64_t m, int64_t k,
+                       int64_t n, int64_t ld, void* stream, spmm_plan_info* info_host) {
+    if (!info_host) return fail(SPMM_ERR_INVALID, "info is NULL");
+    int dev = 0;
+    SPMM_HIP(hipGetDevice(&dev));
+    PlanRef p;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(csr_key(A_rowptr, A_colind, m, k, n, ld, dev, stream));
+        if (it != g_cache.end()) p = it->second;
+    }
+    if (!p) return fail(SPMM_ERR_STATE, "no cached spmm_csr plan for these arguments");
+    fill_info(p.get(), info_host);
+    return SPMM_OK;
 }
 
 int spmm_cache_clear(void) {

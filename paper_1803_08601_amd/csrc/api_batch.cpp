@@ -86,6 +86,11 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
     if (dtype != SPMM_F32 && dtype != SPMM_BF16 && dtype != SPMM_F16)
         return fail(SPMM_ERR_UNSUPPORTED, "dtype %d", dtype);
     if (mode < SPMM_MODE_PAPER || mode > SPMM_MODE_NZSPLIT) return fail(SPMM_ERR_INVALID, "mode %d", mode);
+    for (int64_t i = 0; i < count; ++i) {
+        const spmm_problem& q = problems_host[i];
+        const int rc = check_dims(q.m, q.k, q.nnz, q.n, q.ld);
+        if (rc != SPMM_OK) return fail(rc, "problem %lld: %s", (long long)i, spmm_last_error());
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     spmm_batch_s* b = new (std::nothrow) spmm_batch_s;
@@ -107,6 +112,7 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
         opts.fixed_unroll = spmmk::kBatchUnroll;
         opts.max_W = spmmk::kBatchMaxW;
         opts.rowblock = false;  // the persistent kernel runs row split and merge tiles only
+        opts.no_planes = true;  // ... in its own order of work items
         opts.vals = q.A_vals;
         opts.B = q.B;
         opts.C = q.C;

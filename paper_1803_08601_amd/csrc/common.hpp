@@ -165,4 +165,40 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + idx;
 }
 
+// Processing order of the row tiles (a workgroup's rows) of row split and
+// row blocks for matrices whose entries lie near a few diagonals far apart,
+// such as the neighbour planes of a 3-D stencil (`plane` tiles apart): strips
+// of `strip` consecutive tiles are taken through every plane before the next
+// strip, so a B row that three planes use is reused after about three
+// strips of rows instead of two whole planes. A bijection on
+// [0, planes * plane) (plane a multiple of strip); later tiles keep their
+// place; strip == 0 is the row order. Each row's sum is unchanged.
+struct TileOrder {
+    int64_t plane = 0, strip = 0, planes = 0;
+};
+
+__device__ __forceinline__ int64_t tile_order(int64_t t, const TileOrder& o) {
+    if (o.strip == 0) return t;
+    const int64_t per_strip = o.strip * o.planes;
+    if (t >= o.planes * o.plane) return t;
+    const int64_t s = t / per_strip, r = t - s * per_strip;
+    const int64_t z = r / o.strip, w = r - z * o.strip;
+    return z * o.plane + s * o.strip + w;
+}
+
+// The order for tiles of `tile_rows` rows out of a plan's plane and strip
+// sizes in rows (row order when they are not whole numbers of tiles).
+inline TileOrder make_tile_order(int64_t plane_rows, int64_t strip_rows, int64_t tile_rows,
+                                 int64_t ntiles) {
+    TileOrder o;
+    if (strip_rows <= 0 || plane_rows <= 0 || tile_rows <= 0 || plane_rows % tile_rows ||
+        strip_rows % tile_rows || plane_rows % strip_rows)
+        return o;
+    o.plane = plane_rows / tile_rows;
+    o.strip = strip_rows / tile_rows;
+    o.planes = ntiles / o.plane;
+    if (o.planes < 2) o = TileOrder{};
+    return o;
+}
+
 }  // namespace spmmk

@@ -22,7 +22,17 @@ struct Shape {
     int col_tiles = 1;
     int nz = 0;         // merge walk over nonzero-split pieces (1-D partition)
     int short_addr = 0; // B has < 2^24 rows of < 2^24 bytes and spans < 4 GiB
+    // Row split and row blocks: rows are taken in strips of strip_rows
+    // through planes of plane_rows rows (0: in row order); see TileOrder.
+    int64_t plane_rows = 0, strip_rows = 0;
 };
+
+// Entry offsets colind - row of A: hi = the largest |offset|; near = the
+// largest |offset| below hi / 2; far_lo = the smallest |offset| at or above
+// hi / 2 (two passes; out[0..2] = hi, near, far_lo, out[2] starting at
+// INT_MAX and out[0], out[1] at 0).
+hipError_t launch_offset_stats(const int* rowptr, const int* colind, int64_t m, int* out,
+                               hipStream_t st);
 
 // Operands of one forward product; coords, P and the carry arrays are the
 // merge-based workspace (unused by row split).
@@ -51,6 +61,14 @@ hipError_t launch_forward_semiring(int semiring, int dtype, bool merge, const Sh
 // (nz == 0) or the nonzero split (nz != 0).
 hipError_t launch_merge_partition(const int* rowptr, int64_t m, int64_t nnz, int W, int64_t P,
                                   int nz, int* coords, hipStream_t st);
+
+// Re-check a kept diagonal partition (P + 1 coordinates of W-item pieces for
+// m rows and nnz entries) against rowptr: wrong coordinates are searched
+// again; if rowptr[m] != nnz every piece is emptied, C (m x n, stride ld) is
+// filled with NaN and *flag (host-visible) is set to 1.
+hipError_t launch_merge_revalidate(const int* rowptr, int64_t m, int64_t nnz, int W, int64_t P,
+                                   int* coords, float* C, int64_t n, int64_t ld, int* flag,
+                                   hipStream_t st);
 
 // stats[0] = longest row, stats[1] = rows with >= 1024 entries,
 // stats[2] = 1 if rowptr is non-decreasing with rowptr[0] == 0 else 0.

@@ -62,8 +62,17 @@ struct spmm_plan_s {
     spmmh::MergeWs sddmm_ws;  // merge partition for SDDMM when the kernel is row split
     spmmh::RowBlocks rb;      // ROWBLOCK plans
     int sorted = -1;          // columns strictly increase in every row: 1 / 0 / -1 unknown
+    // plane structure for the tile order of row split and row blocks (plane
+    // distance and strip in rows, 0 when none was found)
+    int64_t found_plane = 0, found_strip = 0;
     spmmh::Transpose tr;
     spmm_plan_s* tplan = nullptr;  // plan over A^T (k rows, m columns)
+    // One-call plans of the merge kernel: a host-visible word the partition
+    // re-check sets when the row offsets passed no longer end at nnz
+    // (pinned host memory and its device address).
+    int* guard_host = nullptr;
+    int* guard_dev = nullptr;
+    int* aux_dev = nullptr;  // one-call plans: row statistics and nnz read back at creation
 };
 
 namespace spmmh {
@@ -87,6 +96,13 @@ struct TuneOpts {
     int fixed_unroll = 0;
     int max_W = 0;  // largest merge piece allowed (0: no limit)
     bool rowblock = true;  // the row-block kernel may be a candidate
+    // row statistics already known (longest row, rows of >= 1024 entries):
+    // no statistics pass
+    bool known_stats = false;
+    int64_t max_row_len = 0, long_rows = 0;
+    bool no_sddmm = false;  // no SDDMM partition for a row-split plan
+    bool no_sync = false;   // do not synchronise the stream at the end
+    bool no_planes = false; // no plane-structure pass (the tile order stays the row order)
     const void* vals = nullptr;
     const void* B = nullptr;
     float* C = nullptr;
@@ -97,5 +113,7 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
                 const spmm_config* forced, hipStream_t st, bool register_plan,
                 const TuneOpts* opts = nullptr);
 void destroy_plan(spmm_plan_s* p);
+// Host checks of sizes (signs, int32 limits, the nnz cap, ld >= max(1, n)).
+int check_dims(int64_t m, int64_t k, int64_t nnz, int64_t n, int64_t ld);
 
 }  // namespace spmmh

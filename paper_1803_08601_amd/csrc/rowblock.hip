@@ -120,7 +120,8 @@ __global__ __launch_bounds__(kBlock) void k_rowblock(const int* __restrict__ row
                                                       const typename S::T* __restrict__ vals,
                                                       const typename S::T* __restrict__ B,
                                                       float* __restrict__ C, int64_t m, int n,
-                                                      int64_t ld, int g_log2, int ts_log2) {
+                                                      int64_t ld, int g_log2, int ts_log2,
+                                                      TileOrder ord) {
     // Each team stages its current chunk (two union entries per lane) here;
     // only lanes of the same wavefront read what a lane wrote.
     __shared__ int s_w[2 * kBlock];
@@ -155,7 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_rowblock(const int* __restrict__ row
 
     const int64_t mb = (m + RB - 1) / RB;
     const int64_t nblk = (mb + (int64_t(1) << teams_log2) - 1) >> teams_log2;
-    for (int64_t blk = xcd_remap(blockIdx.x, gridDim.x); blk < nblk; blk += gridDim.x) {
+    for (int64_t t = xcd_remap(blockIdx.x, gridDim.x); t < nblk; t += gridDim.x) {
+        const int64_t blk = tile_order(t, ord);
         const int64_t b = (blk << teams_log2) + (threadIdx.x >> tl_log2);
         int u0 = 0, u1 = 0;
         int first[RB];  // first value of each row of the block
@@ -311,14 +313,15 @@ static hipError_t rowblock_go(const Shape& s, const ForwardArgs& a, const int* u
     const int64_t mb = (a.m + RB - 1) / RB;
     const int64_t need = (mb + blocks_per_wg - 1) / blocks_per_wg;
     const uint32_t grid = (uint32_t)(need < (1 << 22) ? need : (1 << 22));
+    const TileOrder ord = make_tile_order(s.plane_rows, s.strip_rows, blocks_per_wg * RB, need);
     if (s.short_addr)
         hipLaunchKernelGGL((k_rowblock<S, VEC, U, RB, true>), dim3(grid, s.col_tiles), dim3(kBlock),
                            0, st, a.rowptr, ub_ptr, words, vals, B, a.C, a.m, (int)a.n, a.ld,
-                           s.g_log2, s.ts_log2);
+                           s.g_log2, s.ts_log2, ord);
     else
         hipLaunchKernelGGL((k_rowblock<S, VEC, U, RB, false>), dim3(grid, s.col_tiles),
                            dim3(kBlock), 0, st, a.rowptr, ub_ptr, words, vals, B, a.C, a.m,
-                           (int)a.n, a.ld, s.g_log2, s.ts_log2);
+                           (int)a.n, a.ld, s.g_log2, s.ts_log2, ord);
     return hipGetLastError();
 }
 

@@ -488,12 +488,13 @@ __global__ __launch_bounds__(kBlock) void k_rowsplit(const int* __restrict__ row
                                                       const typename S::T* __restrict__ vals,
                                                       const typename S::T* __restrict__ B,
                                                       float* __restrict__ C, int64_t m, int n,
-                                                      int64_t ld, int g_log2, int ts_log2) {
+                                                      int64_t ld, int g_log2, int ts_log2,
+                                                      TileOrder ord) {
     const int rpb_log2 = (6 - g_log2 - ts_log2) + 2;
     const int64_t nblk = (m + (int64_t(1) << rpb_log2) - 1) >> rpb_log2;
-    for (int64_t blk = xcd_remap(blockIdx.x, gridDim.x); blk < nblk; blk += gridDim.x)
+    for (int64_t t = xcd_remap(blockIdx.x, gridDim.x); t < nblk; t += gridDim.x)
         rowsplit_block<S, VEC, U, R, SHORT>(rowptr, colind, vals, B, C, m, n, ld, g_log2,
-                                            ts_log2, blk, blockIdx.y);
+                                            ts_log2, tile_order(t, ord), blockIdx.y);
 }
 
 template <class S, int VEC, int U, class R, bool NZ>
@@ -531,14 +532,15 @@ hipError_t launch_one(bool merge, const Shape& s, const ForwardArgs& a, hipStrea
         const int64_t rows_per_block = int64_t(kWave >> tl_log2) * (kBlock / kWave);
         const int64_t need = (a.m + rows_per_block - 1) / rows_per_block;
         const uint32_t grid = (uint32_t)(need < (1 << 22) ? need : (1 << 22));
+        const TileOrder ord = make_tile_order(s.plane_rows, s.strip_rows, rows_per_block, need);
         if (s.short_addr)
             hipLaunchKernelGGL((k_rowsplit<S, VEC, U, R, true>), dim3(grid, s.col_tiles),
                                dim3(kBlock), 0, st, a.rowptr, a.colind, vals, B, a.C, a.m,
-                               (int)a.n, a.ld, s.g_log2, s.ts_log2);
+                               (int)a.n, a.ld, s.g_log2, s.ts_log2, ord);
         else
             hipLaunchKernelGGL((k_rowsplit<S, VEC, U, R, false>), dim3(grid, s.col_tiles),
                                dim3(kBlock), 0, st, a.rowptr, a.colind, vals, B, a.C, a.m,
-                               (int)a.n, a.ld, s.g_log2, s.ts_log2);
+                               (int)a.n, a.ld, s.g_log2, s.ts_log2, ord);
     } else {
         const dim3 grid((uint32_t)a.P, s.col_tiles);
         if (s.nz)

@@ -33,7 +33,7 @@ class spmm_config(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("vec", ctypes.c_int32),
                 ("lanes_per_row", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("items_per_wg", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
-                ("rows_per_block", ctypes.c_int32)]
+                ("rows_per_block", ctypes.c_int32), ("tile_order", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -46,7 +46,9 @@ class spmm_plan_info(ctypes.Structure):
                 ("config", spmm_config), ("lanes_per_slot", ctypes.c_int32),
                 ("col_tiles", ctypes.c_int32), ("num_parts", ctypes.c_int64),
                 ("max_row_len", ctypes.c_int64), ("mean_row_len", ctypes.c_double),
-                ("tuned_ms", ctypes.c_double), ("has_transpose", ctypes.c_int32)]
+                ("tuned_ms", ctypes.c_double), ("has_transpose", ctypes.c_int32),
+                ("long_rows", ctypes.c_int64), ("plane_rows", ctypes.c_int64),
+                ("strip_rows", ctypes.c_int64)]
 
 
 class spmm_problem(ctypes.Structure):
@@ -66,6 +68,7 @@ _lib = None
 _VP, _I64, _I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
 _SIGS = {
     "spmm_csr": [_VP, _VP, _VP, _VP, _VP, _I64, _I64, _I64, _I64, _VP],
+    "spmm_csr_plan_info": [_VP, _VP, _I64, _I64, _I64, _I64, _VP, _VP],
     "spmm_cache_clear": [],
     "spmm_plan_create": [_VP, _VP, _VP, _I64, _I64, _I64, _I64, _I64, _I32, _I32, _VP],
     "spmm_plan_create_config": [_VP, _VP, _VP, _I64, _I64, _I64, _I64, _I64, _I32, _VP, _VP],
@@ -155,6 +158,13 @@ def dtype_code(torch_dtype):
 def spmm_csr(A_rowptr, A_colind, A_vals, B, C, m, k, n, ld, stream=None):
     return _check("spmm_csr", lib().spmm_csr(_ptr(A_rowptr), _ptr(A_colind), _ptr(A_vals),
                                              _ptr(B), _ptr(C), m, k, n, ld, _stream(stream)))
+
+
+def spmm_csr_plan_info(A_rowptr, A_colind, m, k, n, ld, stream=None):
+    info = spmm_plan_info()
+    _check("spmm_csr_plan_info", lib().spmm_csr_plan_info(
+        _ptr(A_rowptr), _ptr(A_colind), m, k, n, ld, _stream(stream), ctypes.byref(info)))
+    return info
 
 
 def spmm_cache_clear():

@@ -44,6 +44,10 @@ def _create(**kw):
     (dict(rowptr=None), nv.SPMM_ERR_INVALID),
     (dict(colind=None), nv.SPMM_ERR_INVALID),
     (dict(m=2**31), nv.SPMM_ERR_UNSUPPORTED),
+    # entry indices are int32 with chunk loops stepping past them: nnz is
+    # capped 4096 below 2^31 - 1
+    (dict(nnz=2**31 - 4096), nv.SPMM_ERR_UNSUPPORTED),
+    (dict(nnz=2**31 - 1), nv.SPMM_ERR_UNSUPPORTED),
     (dict(k=0), nv.SPMM_ERR_INVALID),
 ])
 def test_plan_create_rejects(kw, status):
@@ -74,12 +78,32 @@ def test_spmm_csr_noop_and_checks():
     assert L.spmm_csr(None, None, None, None, None, -1, 5, 4, 4, None) == nv.SPMM_ERR_INVALID
 
 
+def test_nnz_cap_on_every_plan_entry_point():
+    L = nv.lib()
+    cfg = nv.spmm_config(kernel=nv.SPMM_KERNEL_MERGE)
+    out = ctypes.byref(ctypes.c_void_p())
+    assert L.spmm_plan_create_config(out, ctypes.c_void_p(8), ctypes.c_void_p(8), 10, 10,
+                                     2**31 - 4000, 4, 4, 0, ctypes.byref(cfg), None) \
+        == nv.SPMM_ERR_UNSUPPORTED
+    assert "2^31 - 4097" in nv.spmm_last_error()
+    assert L.spmm_csr_validate(ctypes.c_void_p(8), ctypes.c_void_p(8), 10, 10, 2**31 - 2,
+                               None) == nv.SPMM_ERR_UNSUPPORTED
+    prob = nv.spmm_problem(8, 8, 8, 8, 8, 10, 10, 2**31 - 100, 4, 4)
+    arr = (nv.spmm_problem * 1)(prob)
+    assert L.spmm_batch_plan(out, arr, 1, 0, 0, None) == nv.SPMM_ERR_UNSUPPORTED
+
+
+def test_csr_plan_info_checks():
+    L = nv.lib()
+    assert L.spmm_csr_plan_info(None, None, 5, 5, 4, 4, None, None) == nv.SPMM_ERR_INVALID
+
+
 def test_config_struct_layout(tmp_path):
     """The ctypes structures match the C header's layout: a C program built
     against include/spmm.h prints every field's offset and each size."""
     import shutil
     import subprocess
-    assert ctypes.sizeof(nv.spmm_config) == 28
+    assert ctypes.sizeof(nv.spmm_config) == 32
     assert ctypes.sizeof(nv.spmm_problem) == 5 * 8 + 5 * 8
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")

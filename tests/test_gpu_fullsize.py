@@ -84,6 +84,37 @@ def test_stencil_full(stencil, n):
         del plan
 
 
+@pytest.mark.parametrize("n", [16, 128])
+def test_stencil_integer_exact_full(stencil, n):
+    """Integer values on the full 128^3 stencil: the whole output of row split
+    and of row blocks of 2, 4 and 8 rows (their union words and the values
+    each word's rank selects, on every row) equals the oracle bit for bit, as
+    does the shape the timed plan picks."""
+    A = wl.CSR(stencil.rowptr, stencil.colind,
+               np.random.default_rng(7).integers(-8, 9, stencil.nnz).astype(np.float32),
+               stencil.m, stencil.k)
+    B = wl.dense(8, A.k, n, kind="int")
+    ref = oracle.spmm(A.rowptr, A.colind, A.vals, B)
+    assert np.abs(ref).max() < 2**24
+    ref32 = ref.astype(np.float32)
+    del ref
+    rp, ci, vt, Bt = dev(A.rowptr), dev(A.colind), dev(A.vals), dev(B)
+    RB = nv.SPMM_KERNEL_ROWBLOCK
+    shapes = [("rowsplit", None), ("autotune", None),
+              ("rb2", dict(kernel=RB, rows_per_block=2)), ("rb4", dict(kernel=RB, rows_per_block=4)),
+              ("rb8", dict(kernel=RB, rows_per_block=8)),
+              ("rb4-32-u4", dict(kernel=RB, rows_per_block=4, lanes_per_row=32, unroll=4))]
+    C = torch.empty(A.m, n, device="cuda")
+    for name, cfg in shapes:
+        plan = nv.Plan(rp, ci, A.m, A.k, n, mode="paper" if cfg else name, config=cfg, nnz=A.nnz)
+        C.fill_(float("nan"))
+        plan.execute(vt, Bt, C)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+        assert np.array_equal(got, ref32), f"{name}: {int((got != ref32).sum())} elements differ"
+        plan.close()
+
+
 def test_power_law_integer_exact_full(power_law):
     """Integer values at full size: the whole output must equal the oracle
     bit for bit, whatever the kernel and order."""
@@ -102,16 +133,27 @@ def test_power_law_integer_exact_full(power_law):
         assert np.array_equal(C.cpu().numpy().astype(np.float64), ref)
 
 
-def test_gcn_bf16_forward_backward_full():
-    A = wl.gcn_adjacency(seed=1004)
+@pytest.fixture(scope="module")
+def gcn():
+    return wl.gcn_adjacency(seed=1004)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_gcn_forward_backward_full(gcn, dtype):
+    """The GCN workload as the benchmark runs it (plan by timing, transpose
+    built once), in float32 and in BF16 storage: sampled forward rows, every
+    entry of dvals, sampled rows of dB (A is symmetric, so A^T dC = A dC
+    row by row from the oracle's product) and the Euler identities."""
+    A = gcn
     n = 128
     B = wl.dense(1004, A.k, n)
     dC = wl.dense(1004, A.m, n, kind="normal", stream=2)
-    vt = dev(A.vals.astype(np.float32), torch.bfloat16)
-    Bt = dev(B, torch.bfloat16)
+    vt = dev(A.vals.astype(np.float32), DT[dtype])
+    Bt = dev(B, DT[dtype])
     dCt = dev(dC)
     rp, ci = dev(A.rowptr), dev(A.colind)
-    plan = nv.Plan(rp, ci, A.m, A.k, n, dtype=nv.SPMM_BF16, mode="autotune", nnz=A.nnz)
+    plan = nv.Plan(rp, ci, A.m, A.k, n, dtype=nv.dtype_code(DT[dtype]), mode="autotune",
+                   nnz=A.nnz)
     C = torch.empty(A.m, n, device="cuda")
     plan.execute(vt, Bt, C)
     plan.transpose_build()
@@ -121,11 +163,13 @@ def test_gcn_bf16_forward_backward_full():
     plan.sddmm(dCt, Bt, dv)
     torch.cuda.synchronize()
     rows = sample_rows(A)
-    check_rows(A, vt, Bt, C, n, rows)  # kernel error on the bf16 inputs
-    # storage error against the fp32/fp64 inputs
-    ref32 = oracle.spmm_rows(A.rowptr, A.colind, A.vals, B, rows)
-    N32 = oracle.spmm_rows(A.rowptr, A.colind, np.abs(A.vals), np.abs(B), rows)
-    assert rel_err(C[torch.from_numpy(rows).cuda()].cpu().numpy(), ref32, N32) <= TOL_STORAGE_16
+    check_rows(A, vt, Bt, C, n, rows)  # kernel error on the stored inputs
+    if dtype != "f32":
+        # storage error against the fp64 values and fp32 B
+        ref32 = oracle.spmm_rows(A.rowptr, A.colind, A.vals, B, rows)
+        N32 = oracle.spmm_rows(A.rowptr, A.colind, np.abs(A.vals), np.abs(B), rows)
+        got = C[torch.from_numpy(rows).cuda()].cpu().numpy()
+        assert rel_err(got, ref32, N32) <= TOL_STORAGE_16
     v, vtag = host_bits(vt)
     b, btag = host_bits(Bt)
     ref_dv = oracle.sddmm(A.rowptr, A.colind, dC, b, b_tag=btag)
@@ -142,10 +186,10 @@ def test_gcn_bf16_forward_backward_full():
     assert abs(float((dv.double() * vt.double()).sum()) - L) <= 1e-5 * scale
 
 
-def test_gcn_transpose_bit_exact_full():
+def test_gcn_transpose_bit_exact_full(gcn):
     """The GPU radix-sort transpose at full size (16.5M entries, three digit
     passes, many scan chunks) equals the oracle's counting sort bit for bit."""
-    A = wl.gcn_adjacency(seed=1004)
+    A = gcn
     rp, ci = dev(A.rowptr), dev(A.colind)
     plan = nv.Plan(rp, ci, A.m, A.k, 8, nnz=A.nnz, mode="rule")
     plan.transpose_build()
