@@ -9,17 +9,24 @@ once before the timed region, as A's structure is fixed across steps; each
 step is one full product (main kernel plus, for merge-based plans, the
 carry-out fix-up pass).
 
-Prints one JSON line: GFLOP/s = 2 nnz n / t over K timed steps, the roofline
-of the main kernel (algorithmic bytes per launch over its event-timed
-duration against 8 TB/s HBM), HBM traffic from committed rocprofv3 counters
-when they match the current kernel sources, and the FP64 CPU oracle timed on
-this host's cores as a baseline.
+Timing: each timed step starts from cold caches - 1 GiB written just before
+it (outside its hipEvents) evicts L2 and the Infinity Cache - and its time
+is the hipEvent interval around the whole product. The warm rate (steps back
+to back, wall clock) is reported beside it.
+
+Prints one JSON line: GFLOP/s = 2 nnz n / t, the roofline of the main kernel
+(algorithmic bytes per launch over its event-timed duration against 8 TB/s
+HBM), the L2-to-fabric traffic from committed rocprofv3 counters when they
+were taken on the current kernel sources, and the FP64 CPU oracle timed on
+this host's cores as a baseline; the other workloads follow under "extra".
 """
 import argparse
 import ctypes
+import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,34 +37,56 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
+TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, scaled by a 1 GiB copy: "
+                  "bytes between the L2 caches and the fabric, which include Infinity Cache "
+                  "(MALL) hits - an upper bound on DRAM traffic, not DRAM traffic itself")
 
 
-def kernel_source_hash(files):
-    """Hash of the sources a kernel is built from (counters taken on another
-    version of them do not describe the current kernel)."""
+def kernel_source_hash():
+    """Hash of the device sources (every .hip and .hpp file of the library):
+    counters taken on another version of them do not describe the kernels."""
     h = hashlib.sha256()
-    for f in files:
-        h.update(open(os.path.join(ROOT, "paper_1803_08601_amd", "csrc", f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_1803_08601_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 
-def counter_traffic(records, key, config):
-    """HBM-side bytes per launch from the rocprofv3 counter records of
-    workload `key`: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the
-    copy calibration. Only a record taken for exactly this launch shape on the
-    current kernel sources applies; otherwise None."""
-    traffic = None
+def load_counters():
+    return json.load(open(COUNTERS)) if os.path.exists(COUNTERS) else {}
+
+
+def counter_record(records, key, config):
+    """The counter record of row `key` taken for exactly this launch shape on
+    the current kernel sources, else None."""
+    sha = kernel_source_hash()
     for r in records.get(key, []):
         rc = r.get("config", {})
-        # a shape field missing from the record (added to the config later)
-        # held its default, 0, when the counters were taken
         same = (all(config.get(k) == v for k, v in rc.items())
                 and all(v == 0 for k, v in config.items() if k not in rc))
-        if same and r.get("kernel_source_sha") == kernel_source_hash(r["files"]):
-            traffic = round(r["fetch_kib"] * 1024.0 * r["fetch_scale"]
-                            + r["write_kib"] * 1024.0 * r["write_scale"])
-            break
-    return traffic
+        if same and r.get("kernel_source_sha") == sha:
+            return r
+    return None
+
+
+def traffic_fields(records, key, config, bmin, bgat, ms):
+    """Counter traffic of one row per launch, its rate over the row's
+    event-timed `ms`, and its ratio to the compulsory bytes (null fields
+    when no current record exists)."""
+    r = counter_record(records, key, config)
+    t = None if r is None else int(round(r["traffic_bytes"]))
+    return {"traffic": t,
+            "traffic_GBs": None if t is None else round(t / (ms * 1e-3) / 1e9, 1),
+            "traffic_over_bytes_min": None if t is None else round(t / bmin, 3),
+            "l2_hit_rate": None if r is None else r.get("l2_hit_rate"),
+            "ta_busy": None if r is None else r.get("ta_busy"),
+            "counter_profile": None if r is None else r.get("profile"),
+            "bytes_min": bmin,
+            "bytes_min_frac": round(bmin / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "gather_model_bytes": bgat,
+            "gather_model_frac": None if bgat is None
+            else round(bgat / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 class HipEvents:
@@ -86,37 +115,69 @@ class HipEvents:
 
 
 def spread(ms):
-    """Median, 10th and 90th percentile of a list of times (ms)."""
-    import numpy as np
+    """Mean, median, 10th and 90th percentile of a list of times (ms)."""
     a = np.asarray(ms, dtype=np.float64)
-    return {"median": round(float(np.median(a)), 4), "p10": round(float(np.percentile(a, 10)), 4),
+    return {"mean": round(float(a.mean()), 4), "median": round(float(np.median(a)), 4),
+            "p10": round(float(np.percentile(a, 10)), 4),
             "p90": round(float(np.percentile(a, 90)), 4)}
 
 
 _SCRUB = None
 
 
-def cold_kernel_ms(plan, vals, B, C, reps=20):
-    """Main-kernel time with L2 and the Infinity Cache flushed before each
-    launch: 1 GiB of writes between launches (outside the timed interval,
-    which is the library's own hipEvent pair around its kernel)."""
+def scrub():
+    """1 GiB of writes: evicts L2 (4 MB per XCD) and the 256 MB Infinity Cache."""
     import torch
-    from paper_1803_08601_amd import native as nv
     global _SCRUB
     if _SCRUB is None:
         _SCRUB = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    _SCRUB.fill_(1.0)
+
+
+def time_steps(run, steps, warmup, library_events=True):
+    """Time `run(ev_before, ev_after)` (one product on torch's current stream;
+    the library may record the two hipEvents around its main kernel, or
+    ignore them): `warmup` untimed runs; `steps` warm runs back to back
+    (wall clock between two device synchronisations); then `steps` cold runs,
+    each after scrub() and bracketed by torch events, with the device
+    synchronised before the first and after the last. Cold launches come
+    last, so a profiler's last `steps` dispatches of a kernel are the cold
+    ones."""
+    import torch
     ev = HipEvents()
-    e0 = [ev.create() for _ in range(reps)]
-    e1 = [ev.create() for _ in range(reps)]
-    stream = torch.cuda.current_stream()
-    for i in range(reps):
-        _SCRUB.fill_(float(i))
-        nv.spmm_execute_events(plan.handle, vals, B, C, e0[i], e1[i], stream)
+    evb = [ev.create() for _ in range(2 * steps)]
+    eva = [ev.create() for _ in range(2 * steps)]
+    t_start = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t_end = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for _ in range(warmup):
+        run(None, None)
     torch.cuda.synchronize()
-    ms = [ev.elapsed_ms(e0[i], e1[i]) for i in range(reps)]
-    for e in e0 + e1:
+    t0 = time.perf_counter()
+    for i in range(steps):
+        run(evb[i], eva[i])
+    torch.cuda.synchronize()
+    warm_wall = (time.perf_counter() - t0) * 1e3 / steps
+    scrub()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        scrub()
+        t_start[i].record()
+        run(evb[steps + i], eva[steps + i])
+        t_end[i].record()
+    torch.cuda.synchronize()
+    cold_wall = (time.perf_counter() - t0) * 1e3 / steps
+
+    def kern(lo):
+        return [ev.elapsed_ms(evb[i], eva[i]) for i in range(lo, lo + steps)]
+    # (events the run did not record are never queried: a failed query would
+    # leave an error for the next runtime call to report)
+    warm_k, cold_k = (kern(0), kern(steps)) if library_events else (None, None)
+    cold_step = [t_start[i].elapsed_time(t_end[i]) for i in range(steps)]
+    for e in evb + eva:
         ev.destroy(e)
-    return ms
+    return {"cold_step": cold_step, "cold_kernel": cold_k or cold_step, "cold_wall": cold_wall,
+            "warm_wall": warm_wall, "warm_kernel": warm_k}
 
 
 def bytes_min(m, k, nnz, n, sv, sb):
@@ -131,41 +192,126 @@ def bytes_gather(m, nnz, n, sv, sb):
     return 4 * (m + 1) + (4 + sv) * nnz + sb * nnz * n + 4 * m * n
 
 
+def main_kernel_patterns(kernel):
+    """Regular expressions of the kernels one product launches (for the
+    profiler's dispatch records), by plan kernel."""
+    if kernel in ("merge", "nzsplit"):
+        return [r"\bk_merge<", r"\bk_merge_fixup<"]
+    return [{"rowsplit": r"\bk_rowsplit<", "rowblock": r"\bk_rowblock<"}[kernel]]
+
+
+WORKLOADS = {
+    "powerlaw": ("power-law CSR 1M x 1M, Zipf 2.1 row lengths mean 16 cap 1e5", 1002),
+    "stencil": ("27-point stencil CSR on 128^3 grid", 1003),
+    "plain": ("uniform CSR 4096 x 4096, 16 per row", 1001),
+}
+
+
 def make_workload(name, n):
     from paper_1803_08601_amd import workloads as wl
     if name == "powerlaw":
         A = wl.power_law(seed=1002)
-        desc = f"power-law CSR 1M x 1M, Zipf 2.1 row lengths mean 16 cap 1e5, n={n}"
     elif name == "stencil":
         A = wl.stencil27(seed=1003)
-        desc = f"27-point stencil CSR on 128^3 grid, n={n}"
     elif name == "plain":
         A = wl.plain(seed=1001)
-        desc = f"uniform CSR 4096 x 4096, 16 per row, n={n}"
     else:
         raise SystemExit(f"unknown workload {name}")
-    B = wl.dense({"powerlaw": 1002, "stencil": 1003, "plain": 1001}[name], A.k, n)
-    return A, B, desc
+    B = wl.dense(WORKLOADS[name][1], A.k, n)
+    return A, B, f"{WORKLOADS[name][0]}, n={n}"
 
 
-def _timed(fn, steps, warmup):
+def single_product(A, B, n, dt, mode="autotune", cfg=None, steps=20, warmup=3, key=None,
+                   records=None, manifest=None):
+    """One planned product timed by time_steps; returns its row (times,
+    GFLOP/s, compulsory and gather-model fractions, counter traffic) and the
+    plan facts."""
     import torch
-    for _ in range(warmup):
-        fn()
+    from paper_1803_08601_amd import native as nv
+    rp, ci = torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colind).cuda()
+    vals = torch.from_numpy(A.vals).to(dt).cuda()
+    Bt = torch.from_numpy(B).to(dt).cuda()
+    C = torch.empty(A.m, n, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps
+    plan = nv.Plan(rp, ci, A.m, A.k, n, ld=n, dtype=nv.dtype_code(dt), mode=mode, config=cfg,
+                   nnz=A.nnz)
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+    kernel = nv.KERNEL_NAMES[info.config.kernel]
+    stream = torch.cuda.current_stream()
+
+    def run(eb, ea):
+        nv.spmm_execute_events(plan.handle, vals, Bt, C, eb, ea, stream)
+    t = time_steps(run, steps, warmup)
+    sz = torch.tensor([], dtype=dt).element_size()
+    bmin = bytes_min(A.m, A.k, A.nnz, n, sz, sz)
+    bgat = bytes_gather(A.m, A.nnz, n, sz, sz)
+    flops = 2.0 * A.nnz * n
+    step = float(np.mean(t["cold_step"]))
+    kms = float(np.mean(t["cold_kernel"]))
+    cfgd = info.config.as_dict()
+    row = {"n": n, "dtype": str(dt).replace("torch.", ""), "nnz": A.nnz, "kernel": kernel,
+           "shape": cfgd, "plan_build_s": round(plan_s, 3),
+           "paper_rule_kernel": "merge" if info.paper_choice else "rowsplit",
+           "ms_per_step": round(step, 4), "gflops": round(flops / (step * 1e-3) / 1e9, 1),
+           "kernel_ms": {"cold": spread(t["cold_kernel"]), "warm": spread(t["warm_kernel"])},
+           "warm": {"ms_per_step": round(t["warm_wall"], 4),
+                    "gflops": round(flops / (t["warm_wall"] * 1e-3) / 1e9, 1)},
+           "tile_order": {"plane_rows": info.plane_rows, "strip_rows": info.strip_rows}}
+    if key is not None:
+        row.update(traffic_fields(records or {}, key, cfgd, bmin, bgat, kms))
+    if manifest is not None:
+        manifest.append({"row": key, "config": cfgd, "steps": steps,
+                         "patterns": main_kernel_patterns(kernel),
+                         "bytes_min": bmin, "bytes_gather": bgat,
+                         "kernel_ms_cold_mean": round(kms, 4)})
+    plan.close()
+    return row, info, t
 
 
-def gcn_fwd_bwd(steps=20, warmup=3):
+def other_configs(A_pl, records, steps=20, warmup=3, only=None, manifest=None):
+    """The remaining single-product workloads, each planned by timing: the
+    uniform 4096 x 4096 matrix with 16 entries per row at n = 32 (a
+    launch-bound size), the power-law matrix at n = 8, the same at n = 64
+    with BF16 storage, and the 27-point stencil on 128^3 at n = 16 and
+    n = 128 (float32); timed as the headline (cold steps, warm beside)."""
+    import torch
+    from paper_1803_08601_amd import workloads as wl
+    out = {}
+    rows = [("plain-n32-f32", "plain", 32, torch.float32),
+            ("powerlaw-n8-f32", "powerlaw", 8, torch.float32),
+            ("powerlaw-n64-bf16", "powerlaw", 64, torch.bfloat16),
+            ("stencil-n16-f32", "stencil", 16, torch.float32),
+            ("stencil-n128-f32", "stencil", 128, torch.float32)]
+    S = None
+    for key, wname, n, dt in rows:
+        if only is not None and key != only:
+            continue
+        if wname == "powerlaw":
+            A = A_pl if A_pl is not None else wl.power_law(seed=1002)
+        elif wname == "stencil":
+            S = S if S is not None else wl.stencil27(seed=1003)
+            A = S
+        else:
+            A = wl.plain(seed=1001)
+        B = wl.dense(WORKLOADS[wname][1], A.k, n)
+        row, _, _ = single_product(A, B, n, dt, steps=steps, warmup=warmup, key=key,
+                                   records=records, manifest=manifest)
+        row["workload"] = f"{WORKLOADS[wname][0]}, n={n}"
+        out[key] = row
+        torch.cuda.empty_cache()
+    return out
+
+
+def gcn_fwd_bwd(records, steps=20, warmup=3, only=None, manifest=None):
     """Differentiable SpMM on the GCN adjacency (500k nodes, mean degree 32,
-    n = 128): one step = forward C = A B, then dB = A^T dC and dvals =
-    SDDMM(dC, B). BF16 storage of vals and B against float32 storage, both
-    with float32 accumulation; accuracy of both is checked by the test suite
-    against the FP64 oracle at full size."""
+    n = 128): forward C = A B, then dB = A^T dC and dvals = SDDMM(dC, B).
+    BF16 storage of vals and B against float32 storage, both with float32
+    accumulation; accuracy of both is checked by the test suite against the
+    FP64 oracle at full size. Each of the three products is timed like the
+    headline (cold steps, warm beside); fwd_bwd is the three back to back
+    (warm). `only` = "f32-fwd", "bf16-dB", ... times just that product."""
     import torch
     from paper_1803_08601_amd import native as nv
     from paper_1803_08601_amd import workloads as wl
@@ -176,7 +322,10 @@ def gcn_fwd_bwd(steps=20, warmup=3):
     rp, ci = torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colind).cuda()
     out = {"workload": "GCN normalised adjacency, 500k nodes, mean degree 32, n=128",
            "nnz": A.nnz}
+    stream = torch.cuda.current_stream()
     for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        if only is not None and not only.startswith(name + "-"):
+            continue
         vals = torch.from_numpy(A.vals.astype(np.float32)).to(dt).cuda()
         Bt = torch.from_numpy(B).to(dt).cuda()
         sv = torch.tensor([], dtype=dt).element_size()
@@ -189,97 +338,71 @@ def gcn_fwd_bwd(steps=20, warmup=3):
         C = torch.empty(A.m, n, device="cuda")
         dB = torch.empty(A.k, n, device="cuda")
         dv = torch.empty(A.nnz, device="cuda")
-        fwd = _timed(lambda: plan.execute(vals, Bt, C), steps, warmup)
-        bwd_b = _timed(lambda: plan.execute_t(vals, dC, dB), steps, warmup)
-        bwd_s = _timed(lambda: plan.execute_t_scatter(vals, dC, dB), steps, warmup)
-        bwd_v = _timed(lambda: plan.sddmm(dC, Bt, dv), steps, warmup)
-
-        def step():
-            plan.execute(vals, Bt, C)
-            plan.execute_t(vals, dC, dB)
-            plan.sddmm(dC, Bt, dv)
-        total = _timed(step, steps, warmup)
-        # compulsory bytes of each product (A, the dense inputs and outputs once)
-        b_fwd = bytes_min(A.m, A.k, A.nnz, n, sv, sv)
-        b_db = 4 * (A.k + 1) + (4 + 4) * A.nnz + (4 + 4 + sv) * A.nnz + 4 * A.m * n + 4 * A.k * n
-        b_dv = 4 * (A.m + 1) + 4 * A.nnz + 4 * A.m * n + sv * A.k * n + 4 * A.nnz
-
-        def gbs(b, ms_):
-            return round(b / (ms_ * 1e-3) / 1e9, 1)
-        out[name] = {"fwd_ms": round(fwd, 4), "dB_ms": round(bwd_b, 4),
-                     "dB_scatter_ms": round(bwd_s, 4), "dvals_ms": round(bwd_v, 4),
-                     "fwd_bwd_ms": round(total, 4), "transpose_build_ms": round(tr_ms, 2),
-                     "fwd_gflops": round(2.0 * A.nnz * n / (fwd * 1e-3) / 1e9, 1),
-                     "algorithmic_GBs": {"fwd": gbs(b_fwd, fwd), "dB": gbs(b_db, bwd_b),
-                                         "dvals": gbs(b_dv, bwd_v)},
-                     "kernel": nv.KERNEL_NAMES[plan.info().config.kernel]}
+        fcfg = plan.info().config.as_dict()
+        fkern = nv.KERNEL_NAMES[fcfg["kernel"]]
+        # the A^T product's plan (same mode) is internal; its kernel shows in
+        # the profile; the record is keyed by the forward plan's shape
+        prods = {
+            "fwd": (lambda eb, ea: nv.spmm_execute_events(plan.handle, vals, Bt, C, eb, ea, stream),
+                    bytes_min(A.m, A.k, A.nnz, n, sv, sv), bytes_gather(A.m, A.nnz, n, sv, sv),
+                    main_kernel_patterns(fkern)),
+            # dB = A^T dC: the value gather (perm: 4, vals: s_v read, float32
+            # written, read again) and the product over A^T with dC float32
+            "dB": (lambda eb, ea: plan.execute_t(vals, dC, dB),
+                   4 * (A.k + 1) + 4 * A.nnz + (4 + sv + 4 + 4) * A.nnz + 4 * A.m * n
+                   + 4 * A.k * n,
+                   4 * (A.k + 1) + 4 * A.nnz + (4 + sv + 4 + 4) * A.nnz + 4 * A.nnz * n
+                   + 4 * A.k * n,
+                   [r"\bk_gather_widen", r"\bk_merge<|\bk_rowsplit<|\bk_rowblock<",
+                    r"\bk_merge_fixup<"]),
+            # dvals: row offsets, column indices, dC once, B, dvals written
+            "dvals": (lambda eb, ea: plan.sddmm(dC, Bt, dv),
+                      4 * (A.m + 1) + 4 * A.nnz + 4 * A.m * n + sv * A.k * n + 4 * A.nnz,
+                      4 * (A.m + 1) + 4 * A.nnz + 4 * A.m * n + sv * A.nnz * n + 4 * A.nnz,
+                      [r"\bk_sddmm<"]),
+        }
+        rec = {"transpose_build_ms": round(tr_ms, 2), "kernel": fkern, "shape": fcfg}
+        for pname, (run, bmin, bgat, pats) in prods.items():
+            key = f"gcn-n128-{name}-{pname}"
+            if only is not None and only != f"{name}-{pname}":
+                continue
+            t = time_steps(run, steps, warmup, library_events=pname == "fwd")
+            ms = float(np.mean(t["cold_step"]))
+            rec[pname] = {"ms_per_step": round(ms, 4),
+                          "gflops": round(2.0 * A.nnz * n / (ms * 1e-3) / 1e9, 1),
+                          "cold_ms": spread(t["cold_step"]),
+                          "warm_ms_per_step": round(t["warm_wall"], 4)}
+            rec[pname].update(traffic_fields(records, key, fcfg, bmin, bgat, ms))
+            if manifest is not None:
+                manifest.append({"row": key, "config": fcfg, "steps": steps, "patterns": pats,
+                                 "bytes_min": bmin, "bytes_gather": bgat,
+                                 "kernel_ms_cold_mean": round(ms, 4)})
+        if only is None:
+            def step():
+                plan.execute(vals, Bt, C)
+                plan.execute_t(vals, dC, dB)
+                plan.sddmm(dC, Bt, dv)
+            t = time_steps(lambda eb, ea: step(), steps, warmup, library_events=False)
+            rec["fwd_bwd_ms"] = round(float(np.mean(t["cold_step"])), 4)
+            rec["fwd_bwd_warm_ms"] = round(t["warm_wall"], 4)
+            rec["dB_scatter_ms"] = round(float(np.mean(time_steps(
+                lambda eb, ea: plan.execute_t_scatter(vals, dC, dB), 5, 1,
+                library_events=False)["cold_step"])), 4)
+        out[name] = rec
         plan.close()
-    out["bf16_speedup_fwd_bwd"] = round(out["f32"]["fwd_bwd_ms"] / out["bf16"]["fwd_bwd_ms"], 3)
-    out["bf16_speedup_fwd"] = round(out["f32"]["fwd_ms"] / out["bf16"]["fwd_ms"], 3)
+    if only is None:
+        out["bf16_speedup_fwd_bwd"] = round(out["f32"]["fwd_bwd_ms"] / out["bf16"]["fwd_bwd_ms"], 3)
+        out["bf16_speedup_fwd"] = round(out["f32"]["fwd"]["ms_per_step"]
+                                        / out["bf16"]["fwd"]["ms_per_step"], 3)
     return out
 
 
-def other_configs(A_pl, steps=20, warmup=3):
-    """The remaining single-product workloads, each planned by timing: the
-    uniform 4096 x 4096 matrix with 16 entries per row at n = 32 (a
-    launch-bound size), the power-law matrix at n = 8, the same at n = 64
-    with BF16 storage, and the 27-point stencil on 128^3 at n = 16 and
-    n = 128 (float32). Main-kernel time from hipEvents, as for the
-    headline, back to back (warm) and with the caches flushed before each
-    launch (cold, median)."""
-    import torch
-    from paper_1803_08601_amd import native as nv
-    from paper_1803_08601_amd import workloads as wl
-    ev = HipEvents()
-    out = {}
-
-    def one(label, A, n, dt, seed):
-        rp, ci = torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colind).cuda()
-        vals = torch.from_numpy(A.vals).to(dt).cuda()
-        Bt = torch.from_numpy(wl.dense(seed, A.k, n)).to(dt).cuda()
-        C = torch.empty(A.m, n, device="cuda")
-        plan = nv.Plan(rp, ci, A.m, A.k, n, dtype=nv.dtype_code(dt), mode="autotune", nnz=A.nnz)
-        stream = torch.cuda.current_stream()
-        for _ in range(warmup):
-            plan.execute(vals, Bt, C)
-        e0 = [ev.create() for _ in range(steps)]
-        e1 = [ev.create() for _ in range(steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(steps):
-            nv.spmm_execute_events(plan.handle, vals, Bt, C, e0[i], e1[i], stream)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
-        kms = float(np.mean([ev.elapsed_ms(e0[i], e1[i]) for i in range(steps)]))
-        for e in e0 + e1:
-            ev.destroy(e)
-        cold = float(np.median(cold_kernel_ms(plan, vals, Bt, C)))
-        sz = torch.tensor([], dtype=dt).element_size()
-        bmin = bytes_min(A.m, A.k, A.nnz, n, sz, sz)
-        out[label] = {"n": n, "dtype": str(dt).replace("torch.", ""), "nnz": A.nnz,
-                      "kernel": nv.KERNEL_NAMES[plan.info().config.kernel],
-                      "ms_per_step": round(ms, 4), "kernel_ms": round(kms, 4),
-                      "cold_kernel_ms": round(cold, 4),
-                      "gflops": round(2.0 * A.nnz * n / (ms * 1e-3) / 1e9, 1),
-                      "roofline_frac": round(bmin / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        plan.close()
-        del rp, ci, vals, Bt, C
-        torch.cuda.empty_cache()
-
-    one("plain_4096_n32_f32", wl.plain(seed=1001), 32, torch.float32, 1001)
-    one("powerlaw_n8_f32", A_pl, 8, torch.float32, 1002)
-    one("powerlaw_n64_bf16", A_pl, 64, torch.bfloat16, 1002)
-    S = wl.stencil27(seed=1003)
-    one("stencil_n16_f32", S, 16, torch.float32, 1003)
-    one("stencil_n128_f32", S, 128, torch.float32, 1003)
-    return out
-
-
-def batched(steps=10, warmup=2):
+def batched(records, steps=10, warmup=2, only=None, manifest=None):
     """512 uneven products (m = k log-uniform in [1e3, 2e5], half U{8..64}
     rows and half Zipf-2.1 rows, n from {8, 32, 128}) in one persistent
     launch replayed from a hipGraph, against the plain float32 kernel called
-    once per problem; float32 and BF16 storage, float32 accumulation."""
+    once per problem; float32 and BF16 storage, float32 accumulation. The
+    graph replays are timed like the headline (cold steps, warm beside)."""
     import torch
     from paper_1803_08601_amd import native as nv
     from paper_1803_08601_amd import workloads as wl
@@ -289,6 +412,8 @@ def batched(steps=10, warmup=2):
            "problems": len(probs), "nnz": int(sum(p.A.nnz for p in probs)), "gflop": round(flops / 1e9, 2)}
     dev = {}
     for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        if only is not None and only != name:
+            continue
         tensors, specs = [], []
         for b, P in enumerate(probs):
             A, n = P.A, P.n
@@ -305,15 +430,25 @@ def batched(steps=10, warmup=2):
         t0 = time.perf_counter()
         h = nv.spmm_batch_plan(specs, nv.dtype_code(dt), nv.SPMM_MODE_AUTOTUNE)
         plan_s = time.perf_counter() - t0
-        ms = _timed(lambda: nv.spmm_batch_run(h), steps, warmup)
+        t = time_steps(lambda eb, ea: nv.spmm_batch_run(h), steps, warmup, library_events=False)
+        ms = float(np.mean(t["cold_step"]))
         cfgs = [nv.spmm_batch_problem_config(h, b) for b in range(len(probs))]
         nv.spmm_batch_destroy(h)
         sv = torch.tensor([], dtype=dt).element_size()
         bmin = sum(bytes_min(P.A.m, P.A.k, P.A.nnz, P.n, sv, sv) for P in probs)
+        bgat = sum(bytes_gather(P.A.m, P.A.nnz, P.n, sv, sv) for P in probs)
         rec = {"graph_ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
-               "algorithmic_GBs": round(bmin / (ms * 1e-3) / 1e9, 1),
+               "cold_ms": spread(t["cold_step"]), "warm_ms_per_step": round(t["warm_wall"], 4),
+               "warm_gflops": round(flops / (t["warm_wall"] * 1e-3) / 1e9, 1),
                "plan_s": round(plan_s, 2), "merge_problems": int(sum(c.kernel for c in cfgs))}
-        if name == "f32":
+        key = f"batch-{name}"
+        rec.update(traffic_fields(records, key, {}, bmin, bgat, ms))
+        if manifest is not None:
+            manifest.append({"row": key, "config": {}, "steps": steps,
+                             "patterns": [r"\bk_batch<", r"\bk_batch_fixup<"],
+                             "bytes_min": bmin, "bytes_gather": bgat,
+                             "kernel_ms_cold_mean": round(ms, 4)})
+        if name == "f32" and only is None:
             # the plain kernel called once per problem: with the batch's own
             # shapes (isolates batching), and with the Sec. 5.4 rule's choice
             for label, mk in (("plain_same_shapes_ms", lambda b, P: dict(config=cfgs[b])),
@@ -324,17 +459,32 @@ def batched(steps=10, warmup=2):
                 def per_problem():
                     for pl, (vt, Bt, C) in zip(plans, tensors):
                         pl.execute(vt, Bt, C)
-                rec[label] = round(_timed(per_problem, 3, 1), 4)
+                rec[label] = round(float(np.mean(time_steps(lambda eb, ea: per_problem(), 3, 1,
+                                                            library_events=False)
+                                                 ["cold_step"])), 4)
                 for pl in plans:
                     pl.close()
         out[name] = rec
         del tensors, specs
-    base = out["f32"]["plain_same_shapes_ms"]
-    out["batched_speedup_vs_plain_f32_same_shapes"] = round(base / out["f32"]["graph_ms"], 3)
-    out["bf16_batched_speedup_vs_plain_f32_same_shapes"] = round(base / out["bf16"]["graph_ms"], 3)
-    out["batched_speedup_vs_plain_f32_paper_rule"] = round(
-        out["f32"]["plain_paper_rule_ms"] / out["f32"]["graph_ms"], 3)
+    if only is None:
+        base = out["f32"]["plain_same_shapes_ms"]
+        out["batched_speedup_vs_plain_f32_same_shapes"] = round(base / out["f32"]["graph_ms"], 3)
+        out["bf16_batched_speedup_vs_plain_f32_same_shapes"] = round(base / out["bf16"]["graph_ms"], 3)
+        out["batched_speedup_vs_plain_f32_paper_rule"] = round(
+            out["f32"]["plain_paper_rule_ms"] / out["f32"]["graph_ms"], 3)
     return out
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
 
 
 def _plan_time(nv, rp, ci, m, k, nnz, n, vals, Bt, C, cfg=None, mode=None, steps=10):
@@ -655,46 +805,245 @@ def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1)):
         torch.cuda.empty_cache()
 
 
+def host_cpu():
+    """CPU model, sockets, cores per socket and threads per core of this
+    host (lscpu), and the threads this process may run on."""
+    info = {"model": "", "sockets": None, "cores_per_socket": None, "threads_per_core": None}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for ln in out.splitlines():
+            key, _, val = ln.partition(":")
+            key, val = key.strip(), val.strip()
+            if key == "Model name":
+                info["model"] = val
+            elif key == "Socket(s)":
+                info["sockets"] = int(val)
+            elif key == "Core(s) per socket":
+                info["cores_per_socket"] = int(val)
+            elif key == "Thread(s) per core":
+                info["threads_per_core"] = int(val)
+    except (OSError, ValueError):
+        pass
+    info["affinity_threads"] = len(os.sched_getaffinity(0))
+    return info
+
+
 def cpu_baseline(A, B, n, budget_s=10.0, max_reps=8):
+    """The FP64 oracle on this host's cores: an -O3 -march=native build of
+    oracle/spmm_oracle.c made here (bitwise the pinned test build), over the
+    full workload - OpenMP over rows on every allowed thread (median of up to
+    `max_reps` passes within `budget_s`) and one pass on one thread."""
+    import tempfile
     import numpy as np
     import oracle
     threads = len(os.sched_getaffinity(0))
+    build = "-O3 -march=native -ffp-contract=off, built on this host"
+    try:
+        lib = oracle.native_build(os.path.join(tempfile.mkdtemp(), "liboracle_native.so"))
+    except Exception as e:  # no compiler on the host: the test build
+        lib, build = None, f"test build -O2 (native build failed: {e})"
     times = []
     t_start = time.perf_counter()
     while len(times) < max_reps and (time.perf_counter() - t_start < budget_s or len(times) < 2):
         t0 = time.perf_counter()
-        oracle.spmm(A.rowptr, A.colind, A.vals, B, n=n, nthreads=threads)
+        oracle.spmm(A.rowptr, A.colind, A.vals, B, n=n, nthreads=threads, library=lib)
         times.append(time.perf_counter() - t0)
     t = float(np.median(times))
-    # one thread on a bounded sample: the first rows holding about an eighth
-    # of the entries (results are identical for any thread count)
-    rows = int(np.searchsorted(A.rowptr, A.nnz // 8))
     t0 = time.perf_counter()
-    oracle.spmm_rows(A.rowptr, A.colind, A.vals, B, np.arange(rows, dtype=np.int64), n=n,
-                     nthreads=1)
+    oracle.spmm(A.rowptr, A.colind, A.vals, B, n=n, nthreads=1, library=lib)
     t1 = time.perf_counter() - t0
-    nnz1 = int(A.rowptr[rows])
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
-                         "")
-    except OSError:
-        pass
     return {"value": 2.0 * A.nnz * n / t / 1e9, "unit": "GFLOP/s", "cores": threads,
             "kind": "oracle",
             "sample": f"full workload, {len(times)} passes of the FP64 oracle (OpenMP over rows, "
-                      f"{threads} threads), median {t * 1e3:.1f} ms per pass",
-            "one_thread": {"value": round(2.0 * nnz1 * n / t1 / 1e9, 3), "unit": "GFLOP/s",
-                           "sample": f"first {rows} rows ({nnz1} entries), one pass"},
-            "cpu_model": model}
+                      f"{threads} threads), median {t * 1e3:.1f} ms per pass; {build}",
+            "one_thread": {"value": round(2.0 * A.nnz * n / t1 / 1e9, 3), "unit": "GFLOP/s",
+                           "sample": f"full workload, one pass on one thread, {t1:.2f} s"},
+            "host": host_cpu()}
+
+
+# ---------------------------------------------------------------- counter records
+
+ROW_FAMILIES = [  # (profile file, title, row-key prefix)
+    ("spmm_powerlaw_1M.md", "Power-law 1M x 1M, mean 16 (k_merge / k_rowsplit)", "powerlaw-"),
+    ("spmm_stencil27_128cube.md", "27-point stencil on 128^3 (k_rowsplit / k_rowblock)", "stencil-"),
+    ("spmm_uniform_4096.md", "Uniform 4096 x 4096, 16 per row (launch-bound size)", "plain-"),
+    ("gcn_500k_n128_fwd_dB_dvals.md", "GCN adjacency 500k nodes, n = 128: forward, dB, dvals",
+     "gcn-"),
+    ("batch_512_problems.md", "512 uneven products in one persistent launch (k_batch)", "batch-"),
+]
+
+
+def read_counter_csv(d):
+    """Dispatches of a rocprofv3 counter run (every *counter_collection.csv
+    under d) in dispatch order: [(kernel name, {counter: value})]."""
+    import csv
+    disp = {}
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                key = (f, int(r["Dispatch_Id"]))
+                name, ctrs = disp.setdefault(key, (r["Kernel_Name"], {}))
+                ctrs[r["Counter_Name"]] = ctrs.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [disp[k] for k in sorted(disp)]
+
+
+def read_kernel_stats(d):
+    """Rows of every *kernel_stats.csv under d: name -> (calls, average us,
+    min us, max us)."""
+    import csv
+    out = {}
+    for f in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                out[r["Name"]] = (int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                                  float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3)
+    return out
+
+
+def last_dispatches(disps, pattern, count):
+    """The last `count` dispatches whose kernel name matches `pattern`."""
+    rx = re.compile(pattern)
+    hit = [c for name, c in disps if rx.search(name)]
+    if len(hit) < count:
+        raise SystemExit(f"record-counters: {len(hit)} dispatches match {pattern!r}, need {count}")
+    return hit[-count:]
+
+
+def mean_counter(dispatches, name):
+    return float(np.mean([c[name] for c in dispatches])) if dispatches else 0.0
+
+
+def copy_scale(d, name, bytes_per_copy):
+    """Counter reading of the plain 1 GiB device copy: bytes moved divided by
+    what `name` reports for one copy (median over its dispatches)."""
+    disps = read_counter_csv(d)
+    names = [n for n, _ in disps]
+    top = max(set(names), key=names.count)
+    vals = [c[name] for n, c in disps if n == top]
+    return bytes_per_copy / (float(np.median(vals)) * 1024.0), top
+
+
+def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
+    """Turn the rocprofv3 runs under run_dir into counter records
+    (profiles/hbm_counters.json) and one summary per workload family.
+    Layout: run_dir/copy/{fetch,write}: `bench.py --copy-calibration` under
+    `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE`; run_dir/<row>/: manifest.json
+    and cmd.txt (the bench arguments) written by the profiled run,
+    fetch/, write/, l2/ (--pmc TCC_HIT_sum TCC_MISS_sum TA_TA_BUSY_avr
+    GRBM_GUI_ACTIVE) and trace/ (--kernel-trace --stats)."""
+    copy_bytes = 256 * 1024 * 1024 * 4
+    fs, fk = copy_scale(os.path.join(run_dir, "copy", "fetch"), "FETCH_SIZE", copy_bytes)
+    ws, _ = copy_scale(os.path.join(run_dir, "copy", "write"), "WRITE_SIZE", copy_bytes)
+    path = os.path.join(profiles, "hbm_counters.json")
+    records = json.load(open(path)) if os.path.exists(path) else {}
+    sha = kernel_source_hash()
+    rows = []
+    for mf in sorted(glob.glob(os.path.join(run_dir, "*", "manifest.json"))):
+        rdir = os.path.dirname(mf)
+        args = open(os.path.join(rdir, "cmd.txt")).read().strip()
+        fetch = read_counter_csv(os.path.join(rdir, "fetch"))
+        write = read_counter_csv(os.path.join(rdir, "write"))
+        l2 = read_counter_csv(os.path.join(rdir, "l2"))
+        stats = read_kernel_stats(os.path.join(rdir, "trace"))
+        for m in json.load(open(mf)):
+            k = m["steps"]
+            per = []
+            for pat in m["patterns"]:
+                f_d = last_dispatches(fetch, pat, k)
+                w_d = last_dispatches(write, pat, k)
+                l_d = last_dispatches(l2, pat, k)
+                rx = re.compile(pat)
+                names = sorted(n for n in stats if rx.search(n))
+                per.append({"pattern": pat, "kernels": names,
+                            "trace_avg_us": [round(stats[n][1], 1) for n in names],
+                            "fetch_kib": mean_counter(f_d, "FETCH_SIZE"),
+                            "write_kib": mean_counter(w_d, "WRITE_SIZE"),
+                            "hit": mean_counter(l_d, "TCC_HIT_sum"),
+                            "miss": mean_counter(l_d, "TCC_MISS_sum"),
+                            "ta": mean_counter(l_d, "TA_TA_BUSY_avr"),
+                            "gui": mean_counter(l_d, "GRBM_GUI_ACTIVE")})
+            fk_ = sum(p["fetch_kib"] for p in per)
+            wk_ = sum(p["write_kib"] for p in per)
+            traffic = fk_ * 1024.0 * fs + wk_ * 1024.0 * ws
+            hits, miss = sum(p["hit"] for p in per), sum(p["miss"] for p in per)
+            main = per[0] if "gather_widen" not in per[0]["pattern"] else per[1]
+            fam = next(f for f in ROW_FAMILIES if m["row"].startswith(f[2]))
+            rec = {"config": m["config"], "kernel_source_sha": sha, "fetch_kib": fk_,
+                   "write_kib": wk_, "fetch_scale": fs, "write_scale": ws,
+                   "traffic_bytes": traffic,
+                   "l2_hit_rate": round(hits / (hits + miss), 4) if hits + miss else None,
+                   "ta_busy": round(main["ta"] / main["gui"], 3) if main["gui"] else None,
+                   "bytes_min": m["bytes_min"], "bytes_gather": m["bytes_gather"],
+                   "kernel_ms_cold_mean": m["kernel_ms_cold_mean"], "profile": fam[0]}
+            lst = [r for r in records.get(m["row"], []) if r.get("config") != m["config"]]
+            records[m["row"]] = [rec] + lst
+            rows.append((fam, m, rec, per, args, stats))
+    with open(path, "w") as fh:
+        json.dump(records, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    rp = "rocprofv3"
+    for fam in ROW_FAMILIES:
+        mine = [r for r in rows if r[0] is fam]
+        if not mine:
+            continue
+        L = [f"# {fam[1]}", "",
+             "Counters per row of `bench.py` (rocprofv3, one MI355X). Traffic = FETCH_SIZE and "
+             "WRITE_SIZE per dispatch of the row's kernels over its last `steps` dispatches (the "
+             "cold-cache steps), scaled by the same counters on a plain 1 GiB copy; it is measured "
+             "between the L2 caches and the fabric, so it includes Infinity Cache hits. Bytes_min: "
+             "A, B and C moved once; gather model: every entry fetching its B row.", "",
+             "Commands (repository root):", "", "```"]
+        for a_ in sorted({r[4] for r in mine}):
+            L += [f"{rp} --kernel-trace --stats --output-format csv -d <run>/<row>/trace -o r -- "
+                  f"python3 bench.py {a_}",
+                  f"{rp} --pmc FETCH_SIZE --output-format csv -d <run>/<row>/fetch -o r -- "
+                  f"python3 bench.py {a_}",
+                  f"{rp} --pmc WRITE_SIZE --output-format csv -d <run>/<row>/write -o r -- "
+                  f"python3 bench.py {a_}",
+                  f"{rp} --pmc TCC_HIT_sum TCC_MISS_sum TA_TA_BUSY_avr GRBM_GUI_ACTIVE "
+                  f"--output-format csv -d <run>/<row>/l2 -o r -- python3 bench.py {a_}"]
+        L += [f"{rp} --pmc FETCH_SIZE --output-format csv -d <run>/copy/fetch -o c -- "
+              "python3 bench.py --copy-calibration",
+              f"{rp} --pmc WRITE_SIZE --output-format csv -d <run>/copy/write -o c -- "
+              "python3 bench.py --copy-calibration",
+              "python3 bench.py --record-counters <run>", "```", "",
+              f"Copy calibration (`{fk[:60]}`): FETCH_SIZE scale {fs:.4f}, WRITE_SIZE scale "
+              f"{ws:.4f}. Kernel sources hash `{sha}`.", "",
+              "| row | shape | cold ms (events) | FETCH KiB | WRITE KiB | traffic GB | "
+              "Bytes_min GB | traffic / Bytes_min | gather model GB | L2 hit | TA busy |",
+              "|---|---|---|---|---|---|---|---|---|---|---|"]
+        for _, m, rec, per, _, _ in mine:
+            L.append(f"| {m['row']} | `{json.dumps(m['config'])}` | {m['kernel_ms_cold_mean']} | "
+                     f"{rec['fetch_kib']:.0f} | {rec['write_kib']:.0f} | "
+                     f"{rec['traffic_bytes'] / 1e9:.3f} | {m['bytes_min'] / 1e9:.3f} | "
+                     f"{rec['traffic_bytes'] / m['bytes_min']:.2f} | {m['bytes_gather'] / 1e9:.3f}"
+                     f" | {rec['l2_hit_rate']} | {rec['ta_busy']} |")
+        L += ["", "Kernels of each row (kernel trace of the same command; average over every "
+              "dispatch of that name, autotuning candidates included):", "",
+              "| row | kernel | calls | avg us | min us | max us | FETCH KiB / dispatch | "
+              "WRITE KiB / dispatch |", "|---|---|---|---|---|---|---|---|"]
+        for _, m, rec, per, _, stats in mine:
+            for p_ in per:
+                for nm in p_["kernels"]:
+                    c, av, mn, mx = stats[nm]
+                    L.append(f"| {m['row']} | `{nm[:110]}` | {c} | {av:.1f} | {mn:.1f} | "
+                             f"{mx:.1f} | {p_['fetch_kib']:.0f} | {p_['write_kib']:.0f} |")
+        with open(os.path.join(profiles, fam[0]), "w") as fh:
+            fh.write("\n".join(L) + "\n")
+    return records
+
+
+ROWS = ["plain-n32-f32", "powerlaw-n8-f32", "powerlaw-n64-bf16", "stencil-n16-f32",
+        "stencil-n128-f32"] + [f"gcn-{d}-{p}" for d in ("f32", "bf16") for p in ("fwd", "dB", "dvals")] \
+    + ["batch-f32", "batch-bf16"]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="powerlaw", choices=["powerlaw", "stencil", "plain"])
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
@@ -706,9 +1055,13 @@ def main():
                          "'{\"kernel\": 1, \"items_per_wg\": 2048, \"unroll\": 2}'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true",
-                    help="only the headline product (skip the GCN fwd+bwd and batched extras)")
-    ap.add_argument("--only-extra", choices=["gcn", "batch", "configs"],
-                    help="run just one extra measurement and print its JSON (for profiling)")
+                    help="only the headline product (skip the other rows)")
+    ap.add_argument("--row", choices=ROWS,
+                    help="time just this row of the extra measurements and print its JSON")
+    ap.add_argument("--manifest", default=None,
+                    help="write the timed rows' kernels and byte counts here (for profiling)")
+    ap.add_argument("--record-counters", default=None, metavar="RUN_DIR",
+                    help="turn rocprofv3 runs under RUN_DIR into profiles/ records and summaries")
     ap.add_argument("--sweep", action="store_true",
                     help="kernel-choice sweep over mean row length (re-derives the Sec. 5.4 threshold)")
     ap.add_argument("--rowblock-sweep", action="store_true",
@@ -728,22 +1081,33 @@ def main():
         print(f"bench.py: the library and this benchmark use one GPU; --gpus {args.gpus} is not "
               "supported (multi-GPU sharding is not implemented)", file=sys.stderr)
         sys.exit(2)
+    if args.record_counters:
+        record_counters(args.record_counters)
+        return
 
-    import numpy as np
     import torch
     from paper_1803_08601_amd import native as nv
+
+    manifest = [] if args.manifest else None
+
+    def write_manifest():
+        if manifest is not None:
+            with open(args.manifest, "w") as fh:
+                json.dump(manifest, fh, indent=1)
 
     if args.sweep:
         heuristic_sweep(args.n)
         return
-    if args.only_extra:
-        if args.only_extra == "configs":
-            from paper_1803_08601_amd import workloads as wl
-            rec = other_configs(wl.power_law(seed=1002), args.steps, args.warmup)
-        elif args.only_extra == "gcn":
-            rec = gcn_fwd_bwd(args.steps, args.warmup)
+    records = load_counters()
+    if args.row:
+        r = args.row
+        if r.startswith("gcn-"):
+            rec = gcn_fwd_bwd(records, args.steps, args.warmup, only=r[4:], manifest=manifest)
+        elif r.startswith("batch-"):
+            rec = batched(records, args.steps, args.warmup, only=r[6:], manifest=manifest)
         else:
-            rec = batched(args.steps, args.warmup)
+            rec = other_configs(None, records, args.steps, args.warmup, only=r, manifest=manifest)
+        write_manifest()
         print(json.dumps(rec), flush=True)
         return
     if args.crossover:
@@ -778,57 +1142,20 @@ def main():
     dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[args.dtype]
     A, B, desc = make_workload(args.workload, args.n)
     n = args.n
-    rp = torch.from_numpy(A.rowptr).cuda()
-    ci = torch.from_numpy(A.colind).cuda()
-    vals = torch.from_numpy(A.vals).to(dt).cuda()
-    Bt = torch.from_numpy(B).to(dt).cuda()
-    C = torch.empty(A.m, n, dtype=torch.float32, device="cuda")
-    torch.cuda.synchronize()
-
-    t0 = time.perf_counter()
     cfg = json.loads(args.config) if args.config else None
-    plan = nv.Plan(rp, ci, A.m, A.k, n, ld=n, dtype=nv.dtype_code(dt), mode=args.mode,
-                   config=cfg, nnz=A.nnz)
-    plan_s = time.perf_counter() - t0
-    info = plan.info()
-    kernel = nv.KERNEL_NAMES[info.config.kernel]
-
-    ev = HipEvents()
-    evb = [ev.create() for _ in range(args.steps)]
-    eva = [ev.create() for _ in range(args.steps)]
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        plan.execute(vals, Bt, C)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        nv.spmm_execute_events(plan.handle, vals, Bt, C, evb[i], eva[i], stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern_ms = [ev.elapsed_ms(evb[i], eva[i]) for i in range(args.steps)]
-    for e in evb + eva:
-        ev.destroy(e)
-
-    # cold-cache launches only in the full run: the profiled commands (--quick)
-    # keep to the warm-up and timed launches
-    cold = None if args.quick else cold_kernel_ms(plan, vals, Bt, C)
-    ms = (t1 - t0) * 1e3 / args.steps
+    key = f"{args.workload}-n{n}-{args.dtype}"
+    row, info, t = single_product(A, B, n, dt, mode=args.mode, cfg=cfg, steps=args.steps,
+                                  warmup=args.warmup, key=key, records=records,
+                                  manifest=manifest)
+    write_manifest()
     flops = 2.0 * A.nnz * n
-    gflops = flops / (ms * 1e-3) / 1e9
-    sv = sb = torch.tensor([], dtype=dt).element_size()
-    bmin = bytes_min(A.m, A.k, A.nnz, n, sv, sb)
-    bgat = bytes_gather(A.m, A.nnz, n, sv, sb)
-    kavg = float(np.mean(kern_ms))
+    ms = float(np.mean(t["cold_step"]))
+    kavg = float(np.mean(t["cold_kernel"]))
+    bmin = row["bytes_min"]
     achieved = bmin / (kavg * 1e-3) / 1e9
-
-    traffic = None
-    if os.path.exists(COUNTERS):
-        traffic = counter_traffic(json.load(open(COUNTERS)), f"{args.workload}-n{n}-{args.dtype}",
-                                  info.config.as_dict())
-
     out = {
         "metric": "SpMM GFLOP/s (2*nnz*n/t)",
-        "value": round(gflops, 2),
+        "value": round(flops / (ms * 1e-3) / 1e9, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -839,38 +1166,41 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
+        "timing": "cold caches: 1 GiB written before each timed step (outside its hipEvents) "
+                  "evicts L2 and the Infinity Cache; a step is the whole product (main kernel "
+                  "and, for merge-based plans, the fix-up), timed by hipEvents around it",
         "config": {"workload": desc, "m": A.m, "k": A.k, "nnz": A.nnz, "n": n,
-                   "kernel": kernel, "mode": "config" if cfg else args.mode,
-                   "shape": info.config.as_dict(),
-                   "paper_rule_kernel": "merge" if info.paper_choice else "rowsplit",
-                   "plan_build_s": round(plan_s, 3), "input_sha": A.digest()},
-        "kernel_ms": {"warm": spread(kern_ms)},
+                   "kernel": row["kernel"], "mode": "config" if cfg else args.mode,
+                   "shape": row["shape"], "paper_rule_kernel": row["paper_rule_kernel"],
+                   "plan_build_s": row["plan_build_s"], "input_sha": A.digest(),
+                   "tile_order": row["tile_order"]},
+        "kernel_ms": row["kernel_ms"],
+        "step_ms": {"cold": spread(t["cold_step"]), "cold_wall_incl_scrub": round(t["cold_wall"], 4)},
+        "warm": {"value": row["warm"]["gflops"], "ms_per_step": row["warm"]["ms_per_step"],
+                 "timing": "steps back to back, wall clock between two synchronisations"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "traffic_GBs": (round(traffic / (kavg * 1e-3) / 1e9, 1)
-                                     if traffic is not None else None),
-                     "kernel": {"rowsplit": "k_rowsplit", "rowblock": "k_rowblock"}.get(kernel,
-                                                                                        "k_merge"),
+                     "traffic": row["traffic"],
+                     "traffic_GBs": row["traffic_GBs"],
+                     "traffic_over_bytes_min": row["traffic_over_bytes_min"],
+                     "traffic_source": TRAFFIC_SOURCE,
+                     "counter_profile": row["counter_profile"],
+                     "l2_hit_rate": row["l2_hit_rate"],
+                     "kernel": {"rowsplit": "k_rowsplit", "rowblock": "k_rowblock"}.get(
+                         row["kernel"], "k_merge"),
                      "kernel_ms": round(kavg, 4), "algorithmic_bytes": bmin,
-                     "gather_model": {"bytes": bgat,
-                                      "achieved": round(bgat / (kavg * 1e-3) / 1e9, 1),
-                                      "frac": round(bgat / (kavg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
+                     "gather_model": {"bytes": row["gather_model_bytes"],
+                                      "achieved": round(row["gather_model_bytes"] / (kavg * 1e-3)
+                                                        / 1e9, 1),
+                                      "frac": row["gather_model_frac"]}},
     }
-    if cold is not None:
-        cmed = float(np.median(cold))
-        out["kernel_ms"].update({"cold": spread(cold),
-                                 "cold_gflops": round(flops / (cmed * 1e-3) / 1e9, 1),
-                                 "cold_roofline_frac": round(bmin / (cmed * 1e-3) / 1e9
-                                                             / HBM_PEAK_GBS, 4)})
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, n)
     if not args.quick:
-        del C, Bt, vals
-        plan.close()
         torch.cuda.empty_cache()
-        out["extra"] = {"other_configs": other_configs(A) if args.workload == "powerlaw" else {},
-                        "gcn_fwd_bwd": gcn_fwd_bwd(), "batched": batched()}
+        out["extra"] = {"other_configs": other_configs(A if args.workload == "powerlaw" else None,
+                                                       records),
+                        "gcn_fwd_bwd": gcn_fwd_bwd(records), "batched": batched(records)}
     print(json.dumps(out), flush=True)
 
 

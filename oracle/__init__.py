@@ -31,33 +31,44 @@ def lib():
         path = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
         if not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(path)
-        i64, i32p, vp, dp = ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p
-        L.oracle_spmm.argtypes = [i64, i64, i64, i32p, i32p, vp, ctypes.c_int, vp, ctypes.c_int,
-                                  i64, dp, i64, ctypes.c_int, ctypes.c_int]
-        L.oracle_spmm_rows.argtypes = [i64, i32p, i32p, vp, ctypes.c_int, vp, ctypes.c_int, i64,
-                                       vp, i64, dp, ctypes.c_int, ctypes.c_int]
-        L.oracle_spmm_t.argtypes = [i64, i64, i64, i32p, i32p, vp, ctypes.c_int, vp, ctypes.c_int,
-                                    i64, dp, ctypes.c_int]
-        L.oracle_sddmm.argtypes = [i64, i64, i32p, i32p, vp, ctypes.c_int, i64, vp, ctypes.c_int,
-                                   i64, dp, ctypes.c_int, ctypes.c_int]
-        L.oracle_spmm_semiring.argtypes = [i64, i64, i32p, i32p, vp, ctypes.c_int, vp, ctypes.c_int,
-                                           i64, dp, i64, ctypes.c_int]
-        L.oracle_transpose.argtypes = [i64, i64, i32p, i32p, i32p, i32p, i32p]
-        L.oracle_merge_walk.argtypes = [i64, i32p, i32p]
-        L.oracle_merge_search.argtypes = [i64, i32p, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
-        L.oracle_merge_num_parts.argtypes = [i64, i64, i64]
-        L.oracle_merge_num_parts.restype = i64
-        L.oracle_merge_partition.argtypes = [i64, i32p, i64, i32p]
-        L.oracle_nz_num_parts.argtypes = [i64, i64, i64]
-        L.oracle_nz_num_parts.restype = i64
-        L.oracle_nz_partition.argtypes = [i64, i32p, i64, i32p]
-        L.oracle_heuristic_merge.argtypes = [i64, i64]
-        L.oracle_decode.argtypes = [vp, i64, ctypes.c_int]
-        L.oracle_decode.restype = ctypes.c_double
-        L.oracle_max_threads.restype = ctypes.c_int
-        _lib = L
+        _lib = load(path)
     return _lib
+
+
+def native_build(path):
+    """The same source compiled -O3 -march=native for this host (the CPU
+    baseline's build; its results are bitwise those of the test build)."""
+    return load(_build.build_native(path))
+
+
+def load(path):
+    """ctypes handle of an oracle library built from spmm_oracle.c."""
+    L = ctypes.CDLL(path)
+    i64, i32p, vp, dp = ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p
+    L.oracle_spmm.argtypes = [i64, i64, i64, i32p, i32p, vp, ctypes.c_int, vp, ctypes.c_int,
+                              i64, dp, i64, ctypes.c_int, ctypes.c_int]
+    L.oracle_spmm_rows.argtypes = [i64, i32p, i32p, vp, ctypes.c_int, vp, ctypes.c_int, i64,
+                                   vp, i64, dp, ctypes.c_int, ctypes.c_int]
+    L.oracle_spmm_t.argtypes = [i64, i64, i64, i32p, i32p, vp, ctypes.c_int, vp, ctypes.c_int,
+                                i64, dp, ctypes.c_int]
+    L.oracle_sddmm.argtypes = [i64, i64, i32p, i32p, vp, ctypes.c_int, i64, vp, ctypes.c_int,
+                               i64, dp, ctypes.c_int, ctypes.c_int]
+    L.oracle_spmm_semiring.argtypes = [i64, i64, i32p, i32p, vp, ctypes.c_int, vp, ctypes.c_int,
+                                       i64, dp, i64, ctypes.c_int]
+    L.oracle_transpose.argtypes = [i64, i64, i32p, i32p, i32p, i32p, i32p]
+    L.oracle_merge_walk.argtypes = [i64, i32p, i32p]
+    L.oracle_merge_search.argtypes = [i64, i32p, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.oracle_merge_num_parts.argtypes = [i64, i64, i64]
+    L.oracle_merge_num_parts.restype = i64
+    L.oracle_merge_partition.argtypes = [i64, i32p, i64, i32p]
+    L.oracle_nz_num_parts.argtypes = [i64, i64, i64]
+    L.oracle_nz_num_parts.restype = i64
+    L.oracle_nz_partition.argtypes = [i64, i32p, i64, i32p]
+    L.oracle_heuristic_merge.argtypes = [i64, i64]
+    L.oracle_decode.argtypes = [vp, i64, ctypes.c_int]
+    L.oracle_decode.restype = ctypes.c_double
+    L.oracle_max_threads.restype = ctypes.c_int
+    return L
 
 
 def _p(a):
@@ -86,8 +97,9 @@ def max_threads():
 
 
 def spmm(rowptr, colind, vals, B, n=None, k=None, vals_tag=None, b_tag=None, absval=False,
-         nthreads=0):
-    """C = A*B in FP64 (m-by-n). ``B`` is k-by-ld row-major; only its first n columns are used."""
+         nthreads=0, library=None):
+    """C = A*B in FP64 (m-by-n). ``B`` is k-by-ld row-major; only its first n columns are used.
+    ``library``: another build of the same source (default: the test build)."""
     rowptr, colind = _csr(rowptr, colind)
     vals, vt = _tagged(vals, vals_tag)
     B, bt = _tagged(B, b_tag)
@@ -95,8 +107,9 @@ def spmm(rowptr, colind, vals, B, n=None, k=None, vals_tag=None, b_tag=None, abs
     kk, ld = B.shape
     n = ld if n is None else n
     C = np.empty((m, n), dtype=np.float64)
-    rc = lib().oracle_spmm(m, kk if k is None else k, n, _p(rowptr), _p(colind), _p(vals), vt,
-                           _p(B), bt, ld, _p(C), n, int(absval), nthreads)
+    rc = (library or lib()).oracle_spmm(m, kk if k is None else k, n, _p(rowptr), _p(colind),
+                                        _p(vals), vt, _p(B), bt, ld, _p(C), n, int(absval),
+                                        nthreads)
     assert rc == 0
     return C
 

@@ -442,3 +442,18 @@ def test_min_plus_bellman_ford_matches_scipy_shortest_paths():
         d = np.minimum(d, relax)
     ref = shortest_path(scipy_of(A), method="BF", directed=True, indices=src).T
     assert np.array_equal(d, ref)
+
+
+def test_native_build_is_bitwise_the_test_build(tmp_path):
+    """The CPU baseline times an -O3 -march=native build of the oracle; it
+    must compute exactly what the pinned test build computes (same double
+    additions in CSR order), at one thread and at all threads."""
+    native = oracle.native_build(str(tmp_path / "liboracle_native.so"))
+    for A, n in ((wl.power_law(seed=41, m=20_000, cap=5_000), 64),
+                 (wl.stencil27(g=16), 16),
+                 (wl.random_csr(42, 3000, 2000, density=0.01, empty_frac=0.2, dup_frac=0.1), 7)):
+        B = wl.dense(43, A.k, n)
+        ref = oracle.spmm(A.rowptr, A.colind, A.vals, B, nthreads=1)
+        for th in (1, 0):
+            got = oracle.spmm(A.rowptr, A.colind, A.vals, B, nthreads=th, library=native)
+            assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
