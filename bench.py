@@ -445,7 +445,7 @@ def batched(records, steps=10, warmup=2, only=None, manifest=None):
         rec.update(traffic_fields(records, key, {}, bmin, bgat, ms))
         if manifest is not None:
             manifest.append({"row": key, "config": {}, "steps": steps,
-                             "patterns": [r"\bk_batch<", r"\bk_batch_fixup<"],
+                             "patterns": [r"\bk_batch<", r"\bk_batch_fixup\b"],
                              "bytes_min": bmin, "bytes_gather": bgat,
                              "kernel_ms_cold_mean": round(ms, 4)})
         if name == "f32" and only is None:
@@ -911,7 +911,10 @@ def last_dispatches(disps, pattern, count):
 
 
 def mean_counter(dispatches, name):
-    return float(np.mean([c[name] for c in dispatches])) if dispatches else 0.0
+    """Mean of one counter over the dispatches (None if the pass lacks it)."""
+    if not dispatches or any(name not in c for c in dispatches):
+        return None
+    return float(np.mean([c[name] for c in dispatches]))
 
 
 def copy_scale(d, name, bytes_per_copy):
@@ -930,7 +933,7 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
     Layout: run_dir/copy/{fetch,write}: `bench.py --copy-calibration` under
     `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE`; run_dir/<row>/: manifest.json
     and cmd.txt (the bench arguments) written by the profiled run,
-    fetch/, write/, l2/ (--pmc TCC_HIT_sum TCC_MISS_sum TA_TA_BUSY_avr
+    fetch/, write/, l2/ (--pmc TCC_HIT_sum TCC_MISS_sum TA_TA_BUSY_sum
     GRBM_GUI_ACTIVE) and trace/ (--kernel-trace --stats)."""
     copy_bytes = 256 * 1024 * 1024 * 4
     fs, fk = copy_scale(os.path.join(run_dir, "copy", "fetch"), "FETCH_SIZE", copy_bytes)
@@ -942,6 +945,16 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
     for mf in sorted(glob.glob(os.path.join(run_dir, "*", "manifest.json"))):
         rdir = os.path.dirname(mf)
         args = open(os.path.join(rdir, "cmd.txt")).read().strip()
+        # the counter passes plan again (by timing): each must have picked
+        # the shapes of the traced run, or its counters describe other kernels
+        for sub in ("fetch", "write", "l2"):
+            smf = os.path.join(rdir, sub + ".manifest.json")
+            if os.path.exists(smf):
+                got = [(x["row"], x["config"]) for x in json.load(open(smf))]
+                want = [(x["row"], x["config"]) for x in json.load(open(mf))]
+                if got != want:
+                    raise SystemExit(f"record-counters: {rdir}/{sub} planned {got}, "
+                                     f"the traced run {want}")
         fetch = read_counter_csv(os.path.join(rdir, "fetch"))
         write = read_counter_csv(os.path.join(rdir, "write"))
         l2 = read_counter_csv(os.path.join(rdir, "l2"))
@@ -961,19 +974,23 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
                             "write_kib": mean_counter(w_d, "WRITE_SIZE"),
                             "hit": mean_counter(l_d, "TCC_HIT_sum"),
                             "miss": mean_counter(l_d, "TCC_MISS_sum"),
-                            "ta": mean_counter(l_d, "TA_TA_BUSY_avr"),
+                            "ta": mean_counter(l_d, "TA_TA_BUSY_sum"),
                             "gui": mean_counter(l_d, "GRBM_GUI_ACTIVE")})
             fk_ = sum(p["fetch_kib"] for p in per)
             wk_ = sum(p["write_kib"] for p in per)
             traffic = fk_ * 1024.0 * fs + wk_ * 1024.0 * ws
             hits, miss = sum(p["hit"] for p in per), sum(p["miss"] for p in per)
             main = per[0] if "gather_widen" not in per[0]["pattern"] else per[1]
+            # TA busy: TA_TA_BUSY_sum over 256 TAs against GRBM_GUI_ACTIVE over
+            # 8 XCDs (the fraction of the kernel's cycles each TA was busy)
+            ta = (main["ta"] / 256.0 / (main["gui"] / 8.0)
+                  if main["ta"] is not None and main["gui"] else None)
             fam = next(f for f in ROW_FAMILIES if m["row"].startswith(f[2]))
             rec = {"config": m["config"], "kernel_source_sha": sha, "fetch_kib": fk_,
                    "write_kib": wk_, "fetch_scale": fs, "write_scale": ws,
                    "traffic_bytes": traffic,
                    "l2_hit_rate": round(hits / (hits + miss), 4) if hits + miss else None,
-                   "ta_busy": round(main["ta"] / main["gui"], 3) if main["gui"] else None,
+                   "ta_busy": None if ta is None else round(ta, 3),
                    "bytes_min": m["bytes_min"], "bytes_gather": m["bytes_gather"],
                    "kernel_ms_cold_mean": m["kernel_ms_cold_mean"], "profile": fam[0]}
             lst = [r for r in records.get(m["row"], []) if r.get("config") != m["config"]]
@@ -995,14 +1012,16 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
              "A, B and C moved once; gather model: every entry fetching its B row.", "",
              "Commands (repository root):", "", "```"]
         for a_ in sorted({r[4] for r in mine}):
+            tc = "--tune-cache <run>/<row>/tune.txt"
             L += [f"{rp} --kernel-trace --stats --output-format csv -d <run>/<row>/trace -o r -- "
-                  f"python3 bench.py {a_}",
+                  f"python3 bench.py {a_} {tc} --manifest <run>/<row>/manifest.json",
                   f"{rp} --pmc FETCH_SIZE --output-format csv -d <run>/<row>/fetch -o r -- "
-                  f"python3 bench.py {a_}",
+                  f"python3 bench.py {a_} {tc} --manifest <run>/<row>/fetch.manifest.json",
                   f"{rp} --pmc WRITE_SIZE --output-format csv -d <run>/<row>/write -o r -- "
-                  f"python3 bench.py {a_}",
-                  f"{rp} --pmc TCC_HIT_sum TCC_MISS_sum TA_TA_BUSY_avr GRBM_GUI_ACTIVE "
-                  f"--output-format csv -d <run>/<row>/l2 -o r -- python3 bench.py {a_}"]
+                  f"python3 bench.py {a_} {tc} --manifest <run>/<row>/write.manifest.json",
+                  f"{rp} --pmc TCC_HIT_sum TCC_MISS_sum TA_TA_BUSY_sum GRBM_GUI_ACTIVE "
+                  f"--output-format csv -d <run>/<row>/l2 -o r -- python3 bench.py {a_} {tc} "
+                  f"--manifest <run>/<row>/l2.manifest.json"]
         L += [f"{rp} --pmc FETCH_SIZE --output-format csv -d <run>/copy/fetch -o c -- "
               "python3 bench.py --copy-calibration",
               f"{rp} --pmc WRITE_SIZE --output-format csv -d <run>/copy/write -o c -- "
@@ -1075,6 +1094,10 @@ def main():
                     help="sparse versus dense product over density (100k x 100k, n = 64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--tune-cache", default=None, metavar="FILE",
+                    help="load the autotuner's choices from FILE if it exists and save them "
+                         "there at exit (profiling passes then plan the shapes the traced "
+                         "run timed)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -1088,6 +1111,11 @@ def main():
     import torch
     from paper_1803_08601_amd import native as nv
 
+    if args.tune_cache:
+        import atexit
+        if os.path.exists(args.tune_cache):
+            nv.spmm_tune_cache_load(args.tune_cache)
+        atexit.register(nv.spmm_tune_cache_save, args.tune_cache)
     manifest = [] if args.manifest else None
 
     def write_manifest():

@@ -228,6 +228,19 @@ int spmm_csr_plan_info(const int32_t* A_rowptr, const int32_t* A_colind, int64_t
 /* Drop every cached plan of spmm_csr (frees their workspace). */
 int spmm_cache_clear(void);
 
+/* Autotuner results kept across processes. The autotuner remembers, per
+ * process, the shape it chose for each key (device, m, k, nnz, n, ld,
+ * longest row, rows of >= 1024 entries, dtype, unroll, largest merge piece,
+ * row blocks allowed); a plan with a known key takes that shape without
+ * timing trials. spmm_tune_cache_save writes every remembered choice to the
+ * text file path_host; spmm_tune_cache_load adds a file's choices (a later
+ * entry for one key replaces an earlier one). A loaded shape is checked like
+ * a forced config when a plan would use it and ignored (tuned afresh) if it
+ * does not fit. Returns SPMM_ERR_INVALID for an unreadable, unwritable or
+ * malformed file (nothing is loaded then). */
+int spmm_tune_cache_save(const char* path_host);
+int spmm_tune_cache_load(const char* path_host);
+
 /* ---------------------------------------------------------------- plans
  * Create a plan for the structure (A_rowptr, A_colind) with nnz nonzeros
  * (nnz must equal A_rowptr[m]; given by the caller so no read-back is

@@ -438,9 +438,14 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
             found = p.sorted == 1;
         }
         if (found) {
-            p.cfg = hit.first;
-            p.tuned_ms = hit.second;
-            return SPMM_OK;
+            // entries loaded from a file pass the checks of a forced shape;
+            // one this matrix cannot use is tuned afresh
+            spmm_config c = hit.first;
+            if (check_config(p, c) == SPMM_OK) {
+                p.cfg = c;
+                p.tuned_ms = hit.second;
+                return SPMM_OK;
+            }
         }
     }
     if (p.m == 0 || p.n == 0) {
@@ -1059,6 +1064,72 @@ int spmm_cache_clear(void) {
         g_cache.clear();
         g_cache_order.clear();
     }
+    return SPMM_OK;
+}
+
+int spmm_tune_cache_save(const char* path_host) {
+    if (!path_host) return fail(SPMM_ERR_INVALID, "path is NULL");
+    std::vector<std::pair<TuneKey, std::pair<spmm_config, double>>> all;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        all.assign(g_tuned.begin(), g_tuned.end());
+    }
+    FILE* f = fopen(path_host, "w");
+    if (!f) return fail(SPMM_ERR_INVALID, "cannot write %s", path_host);
+    fprintf(f, "spmm-tune-cache 1\n");
+    for (const auto& kv : all) {
+        const TuneKey& k = kv.first;
+        const spmm_config& c = kv.second.first;
+        fprintf(f, "%d %lld %lld %lld %lld %lld %lld %lld %d %d %d %d  %d %d %d %d %d %d %d %d  %.9g\n",
+                k.device, (long long)k.m, (long long)k.k, (long long)k.nnz, (long long)k.n,
+                (long long)k.ld, (long long)k.maxrow, (long long)k.longrows, k.dtype, k.unroll,
+                k.max_W, k.rowblock ? 1 : 0, c.kernel, c.vec, c.lanes_per_row, c.unroll,
+                c.items_per_wg, c.tile_cols, c.rows_per_block, c.tile_order, kv.second.second);
+    }
+    const bool ok = fclose(f) == 0;
+    return ok ? SPMM_OK : fail(SPMM_ERR_INVALID, "cannot write %s", path_host);
+}
+
+int spmm_tune_cache_load(const char* path_host) {
+    if (!path_host) return fail(SPMM_ERR_INVALID, "path is NULL");
+    FILE* f = fopen(path_host, "r");
+    if (!f) return fail(SPMM_ERR_INVALID, "cannot read %s", path_host);
+    int version = 0;
+    if (fscanf(f, "spmm-tune-cache %d", &version) != 1 || version != 1) {
+        fclose(f);
+        return fail(SPMM_ERR_INVALID, "%s is not a version-1 tune cache", path_host);
+    }
+    std::vector<std::pair<TuneKey, std::pair<spmm_config, double>>> got;
+    for (;;) {
+        TuneKey k{};
+        spmm_config c{};
+        long long m, kk, nnz, n, ld, maxrow, longrows;
+        int rowblock = 0;
+        double ms = 0.0;
+        const int r = fscanf(f, "%d %lld %lld %lld %lld %lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %lf",
+                             &k.device, &m, &kk, &nnz, &n, &ld, &maxrow, &longrows, &k.dtype,
+                             &k.unroll, &k.max_W, &rowblock, &c.kernel, &c.vec, &c.lanes_per_row,
+                             &c.unroll, &c.items_per_wg, &c.tile_cols, &c.rows_per_block,
+                             &c.tile_order, &ms);
+        if (r == EOF) break;
+        if (r != 21) {
+            fclose(f);
+            return fail(SPMM_ERR_INVALID, "%s: malformed entry %zu", path_host, got.size() + 1);
+        }
+        k.m = m; k.k = kk; k.nnz = nnz; k.n = n; k.ld = ld; k.maxrow = maxrow;
+        k.longrows = longrows; k.rowblock = rowblock != 0;
+        got.push_back({k, {c, ms}});
+    }
+    fclose(f);
+    // each entry passes the same shape checks as a forced config when a plan
+    // uses it; here only the kernel id is checked
+    for (const auto& kv : got)
+        if (kv.second.first.kernel < SPMM_KERNEL_ROWSPLIT ||
+            kv.second.first.kernel > SPMM_KERNEL_ROWBLOCK)
+            return fail(SPMM_ERR_INVALID, "%s: kernel %d is not a kernel", path_host,
+                        kv.second.first.kernel);
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& kv : got) g_tuned[kv.first] = kv.second;
     return SPMM_OK;
 }
 

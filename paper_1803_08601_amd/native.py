@@ -70,6 +70,8 @@ _SIGS = {
     "spmm_csr": [_VP, _VP, _VP, _VP, _VP, _I64, _I64, _I64, _I64, _VP],
     "spmm_csr_plan_info": [_VP, _VP, _I64, _I64, _I64, _I64, _VP, _VP],
     "spmm_cache_clear": [],
+    "spmm_tune_cache_save": [ctypes.c_char_p],
+    "spmm_tune_cache_load": [ctypes.c_char_p],
     "spmm_plan_create": [_VP, _VP, _VP, _I64, _I64, _I64, _I64, _I64, _I32, _I32, _VP],
     "spmm_plan_create_config": [_VP, _VP, _VP, _I64, _I64, _I64, _I64, _I64, _I32, _VP, _VP],
     "spmm_execute": [_VP, _VP, _VP, _VP, _VP],
@@ -169,6 +171,14 @@ def spmm_csr_plan_info(A_rowptr, A_colind, m, k, n, ld, stream=None):
 
 def spmm_cache_clear():
     return _check("spmm_cache_clear", lib().spmm_cache_clear())
+
+
+def spmm_tune_cache_save(path):
+    return _check("spmm_tune_cache_save", lib().spmm_tune_cache_save(os.fsencode(path)))
+
+
+def spmm_tune_cache_load(path):
+    return _check("spmm_tune_cache_load", lib().spmm_tune_cache_load(os.fsencode(path)))
 
 
 def spmm_plan_create(A_rowptr, A_colind, m, k, nnz, n, ld, dtype, mode, stream=None):

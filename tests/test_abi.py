@@ -126,3 +126,26 @@ def test_config_struct_layout(tmp_path):
         assert int(out[name]) == ctypes.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """A loaded tune-cache entry is kept and written back unchanged; files that
+    are missing, of another format or malformed are refused."""
+    line = "0 100 100 900 8 8 20 0 0 0 0 1  1 4 8 2 2048 0 0 0  0.25"
+    f = tmp_path / "t.txt"
+    f.write_text("spmm-tune-cache 1\n" + line + "\n")
+    nv.spmm_tune_cache_load(str(f))
+    g = tmp_path / "u.txt"
+    nv.spmm_tune_cache_save(str(g))
+    rows = g.read_text().splitlines()
+    assert rows[0] == "spmm-tune-cache 1"
+    assert [r.split() for r in rows[1:]].count(line.split()) == 1
+    bad = tmp_path / "bad.txt"
+    for text in ("spmm-tune-cache 1\n1 2 3\n", "spmm-tune-cache 2\n", "something else\n",
+                 "spmm-tune-cache 1\n" + line.replace(" 1 4 8 2", " 7 4 8 2") + "\n"):
+        bad.write_text(text)
+        with pytest.raises(nv.SpmmError) as ei:
+            nv.spmm_tune_cache_load(str(bad))
+        assert ei.value.status == nv.SPMM_ERR_INVALID
+    with pytest.raises(nv.SpmmError):
+        nv.spmm_tune_cache_load(str(tmp_path / "missing.txt"))

@@ -6,6 +6,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -76,8 +77,10 @@ def test_record_counters_from_profiler_output(tmp_path):
         _counter_csv(str(rowd / sub / "r_counter_collection.csv"),
                      [(nm, {ctr: v}) for nm, v in zip(seq, vals[ctr])])
     _counter_csv(str(rowd / "l2" / "r_counter_collection.csv"),
-                 [(nm, {"TCC_HIT_sum": 1.0, "TCC_MISS_sum": 3.0, "TA_TA_BUSY_avr": 50.0,
-                        "GRBM_GUI_ACTIVE": 100.0}) for nm in seq])
+                 [(nm, {"TCC_HIT_sum": 1.0, "TCC_MISS_sum": 3.0,
+                        # busy half the time: 256 TAs, GUI_ACTIVE summed over 8 XCDs
+                        "TA_TA_BUSY_sum": 0.5 * 256 * 100.0 / 8, "GRBM_GUI_ACTIVE": 100.0})
+                  for nm in seq])
     os.makedirs(rowd / "trace")
     with open(rowd / "trace" / "r_kernel_stats.csv", "w", newline="") as fh:
         w = csv.writer(fh)
@@ -103,6 +106,11 @@ def test_record_counters_from_profiler_output(tmp_path):
     text = (prof / r["profile"]).read_text()
     assert "python3 bench.py --quick --no-cpu-baseline --steps 2 --warmup 1" in text
     assert "powerlaw-n64-f32" in text
+    # a counter pass that planned another shape than the traced run is refused
+    (rowd / "fetch.manifest.json").write_text(json.dumps([{
+        "row": "powerlaw-n64-f32", "config": {"kernel": 0, "vec": 4}}]))
+    with pytest.raises(SystemExit, match="planned"):
+        bench.record_counters(str(run), profiles=str(prof))
     assert bench.counter_record(json.load(open(prof / "hbm_counters.json")),
                                 "powerlaw-n64-f32", cfg) is not None
 
