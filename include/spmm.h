@@ -219,6 +219,33 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
              const float* B, float* C, int64_t m, int64_t k, int64_t n, int64_t ld,
              void* stream);
 
+/* ---------------------------------------------------------------- no allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): C = A * B
+ * in float32 like spmm_csr, with no allocation of any kind, no host
+ * synchronisation and no plan cache.
+ *
+ * Differences from spmm_csr: the caller passes nnz (it must equal
+ * A_rowptr[m]; nothing is read back), and the kernel is the Sec. 5.4 choice
+ * of the paper - merge-based iff 100 * nnz < 935 * m, row split otherwise -
+ * with that kernel's default shape, rows in row order. The merge-based
+ * kernel's workspace (P + 1 merge-path coordinates, P carry-out row ids and
+ * P carry-out rows of n floats, P = ceil((m + nnz) / W) pieces of W items)
+ * lives in one static device array of SPMM_NOALLOC_SCRATCH_BYTES per GPU,
+ * held from the library's first use on that GPU until the process ends.
+ * Sizes whose workspace exceeds it return SPMM_ERR_UNSUPPORTED before any
+ * launch (use spmm_csr or a plan then). Row split uses no workspace.
+ *
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap in time on one GPU (two streams, two host
+ * threads) race and give wrong results; serialise them. Results equal
+ * spmm_csr's within the float32 tolerance of summation order (bitwise when
+ * both pick the same kernel and shape). */
+#define SPMM_NOALLOC_SCRATCH_BYTES (64 << 20)
+int spmm_csr_noalloc(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_vals,
+                     const float* B, float* C, int64_t m, int64_t k, int64_t nnz, int64_t n,
+                     int64_t ld, void* stream);
+
 /* Facts of the plan spmm_csr holds for these arguments (the same key; the
  * current device): kernel, shape, row statistics. SPMM_ERR_STATE when no
  * such plan is cached. */

@@ -858,6 +858,34 @@ static int csr_create(const int32_t* A_rowptr, const int32_t* A_colind, int64_t 
     return SPMM_OK;
 }
 
+// ------------------------------------------------------------------ no allocation
+
+// Device memory of spmm_csr_noalloc: the merge-path coordinates, carry-out
+// row ids and carry-out rows of one call. Every device holds its own copy at
+// its own address for the life of the process; host code never uses the
+// name itself (a host-side stand-in), only the address hipGetSymbolAddress
+// returns with that device current, kept per device below.
+static __device__ __align__(256) unsigned char scratch[SPMM_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char*> g_scratch_addr;
+
+static int scratch_address(int dev, unsigned char** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(SPMM_ERR_HIP, "hipGetSymbolAddress(scratch) gave NULL");
+        it = g_scratch_addr.emplace(dev, static_cast<unsigned char*>(ptr)).first;
+    }
+    *out = it->second;
+    return SPMM_OK;
+}
+
+static int64_t round256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
 static CacheKey csr_key(const int32_t* A_rowptr, const int32_t* A_colind, int64_t m, int64_t k,
                         int64_t n, int64_t ld, int dev, void* stream) {
     // keyed by stream too: a merge-based plan's workspace must not be shared
@@ -1038,6 +1066,59 @@ int spmm_csr(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_va
         if (e != hipSuccess) return hip_fail(e, "partition re-check launch");
     }
     return forward(*p, A_rowptr, A_colind, A_vals, B, C, st);
+}
+
+int spmm_csr_noalloc(const int32_t* A_rowptr, const int32_t* A_colind, const float* A_vals,
+                     const float* B, float* C, int64_t m, int64_t k, int64_t nnz, int64_t n,
+                     int64_t ld, void* stream) {
+    int rc = check_dims(m, k, nnz, n, ld);
+    if (rc) return rc;
+    if (m == 0 || n == 0) return SPMM_OK;
+    if (!A_rowptr || !C) return fail(SPMM_ERR_INVALID, "A_rowptr or C is NULL");
+    if (nnz > 0 && (!A_colind || !A_vals || !B))
+        return fail(SPMM_ERR_INVALID, "A_colind, A_vals or B is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // A plan on the stack: the Sec. 5.4 choice from m and nnz, the default
+    // shape of that kernel, no row statistics and no tile order (each would
+    // need a read-back), and, for the merge-based kernel, its workspace in
+    // this device's static scratch.
+    spmm_plan_s p;
+    p.rowptr = A_rowptr;
+    p.colind = A_colind;
+    p.m = m; p.k = k; p.nnz = nnz; p.n = n; p.ld = ld;
+    p.dtype = SPMM_F32;
+    p.mode = SPMM_MODE_PAPER;
+    p.paper_choice = 100 * nnz < 935 * m ? SPMM_KERNEL_MERGE : SPMM_KERNEL_ROWSPLIT;
+    p.cfg = spmm_config{p.paper_choice, 0, 0, 0, 0, 0};
+    rc = check_config(p, p.cfg);
+    if (rc) return rc;
+    if (is_merge(p.cfg.kernel)) {
+        const int64_t P = num_pieces(m, nnz, p.cfg.items_per_wg, false);
+        const int64_t coords_b = round256(int64_t(sizeof(int)) * 2 * (P + 1));
+        const int64_t rows_b = round256(int64_t(sizeof(int)) * P);
+        const int64_t vals_b = int64_t(sizeof(float)) * P * n;
+        if (coords_b + rows_b + vals_b > int64_t(SPMM_NOALLOC_SCRATCH_BYTES))
+            return fail(SPMM_ERR_UNSUPPORTED,
+                        "spmm_csr_noalloc: %lld merge pieces of %d items at n = %lld need %lld "
+                        "bytes of scratch, more than its %lld",
+                        (long long)P, p.cfg.items_per_wg, (long long)n,
+                        (long long)(coords_b + rows_b + vals_b),
+                        (long long)SPMM_NOALLOC_SCRATCH_BYTES);
+        SPMM_HIP(hipGetDevice(&p.device));
+        unsigned char* base = nullptr;
+        rc = scratch_address(p.device, &base);
+        if (rc) return rc;
+        p.ws.coords = reinterpret_cast<int*>(base);
+        p.ws.carry_rows = reinterpret_cast<int*>(base + coords_b);
+        p.ws.carry_vals = reinterpret_cast<float*>(base + coords_b + rows_b);
+        p.ws.P = P;
+        // every coordinate and carry-out row id is written before it is read
+        // (an open row's carry-out values too), so nothing needs clearing
+        const hipError_t e = spmmk::launch_merge_partition(A_rowptr, m, nnz, p.cfg.items_per_wg,
+                                                           P, 0, p.ws.coords, st);
+        if (e != hipSuccess) return hip_fail(e, "merge partition launch");
+    }
+    return forward(p, A_rowptr, A_colind, A_vals, B, C, st);
 }
 
 int spmm_csr_plan_info(const int32_t* A_rowptr, const int32_t* A_colind, int64_t m, int64_t k,

@@ -68,6 +68,7 @@ _lib = None
 _VP, _I64, _I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
 _SIGS = {
     "spmm_csr": [_VP, _VP, _VP, _VP, _VP, _I64, _I64, _I64, _I64, _VP],
+    "spmm_csr_noalloc": [_VP, _VP, _VP, _VP, _VP, _I64, _I64, _I64, _I64, _I64, _VP],
     "spmm_csr_plan_info": [_VP, _VP, _I64, _I64, _I64, _I64, _VP, _VP],
     "spmm_cache_clear": [],
     "spmm_tune_cache_save": [ctypes.c_char_p],
@@ -160,6 +161,12 @@ def dtype_code(torch_dtype):
 def spmm_csr(A_rowptr, A_colind, A_vals, B, C, m, k, n, ld, stream=None):
     return _check("spmm_csr", lib().spmm_csr(_ptr(A_rowptr), _ptr(A_colind), _ptr(A_vals),
                                              _ptr(B), _ptr(C), m, k, n, ld, _stream(stream)))
+
+
+def spmm_csr_noalloc(A_rowptr, A_colind, A_vals, B, C, m, k, nnz, n, ld, stream=None):
+    return _check("spmm_csr_noalloc", lib().spmm_csr_noalloc(
+        _ptr(A_rowptr), _ptr(A_colind), _ptr(A_vals), _ptr(B), _ptr(C), m, k, nnz, n, ld,
+        _stream(stream)))
 
 
 def spmm_csr_plan_info(A_rowptr, A_colind, m, k, n, ld, stream=None):

@@ -128,6 +128,41 @@ def test_config_struct_layout(tmp_path):
             assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"
 
 
+def _noalloc(**kw):
+    a = dict(rowptr=ctypes.c_void_p(256), colind=ctypes.c_void_p(256),
+             vals=ctypes.c_void_p(256), B=ctypes.c_void_p(256), C=ctypes.c_void_p(256),
+             m=10, k=10, nnz=20, n=4, ld=4)
+    a.update(kw)
+    return nv.lib().spmm_csr_noalloc(a["rowptr"], a["colind"], a["vals"], a["B"], a["C"],
+                                     a["m"], a["k"], a["nnz"], a["n"], a["ld"], None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(m=-1), nv.SPMM_ERR_INVALID),
+    (dict(ld=3), nv.SPMM_ERR_INVALID),
+    (dict(nnz=-1), nv.SPMM_ERR_INVALID),
+    (dict(nnz=2**31 - 1), nv.SPMM_ERR_UNSUPPORTED),
+    (dict(C=None), nv.SPMM_ERR_INVALID),
+    (dict(rowptr=None), nv.SPMM_ERR_INVALID),
+    (dict(B=None), nv.SPMM_ERR_INVALID),
+    # merge-based (nnz / m < 9.35): 4883 pieces of 1024 items with carry-out
+    # rows of 4096 floats need 80 MB, more than the 64 MiB static scratch
+    (dict(m=5_000_000, k=1, nnz=0, n=4096, ld=4096), nv.SPMM_ERR_UNSUPPORTED),
+])
+def test_noalloc_rejects_before_any_hip_call(kw, status):
+    """spmm_csr_noalloc refuses bad sizes, null pointers and workspaces larger
+    than its static scratch on the host (the pointers here are never used)."""
+    assert _noalloc(**kw) == status
+    assert nv.spmm_last_error()
+    if kw.get("n") == 4096:
+        assert "scratch" in nv.spmm_last_error()
+
+
+def test_noalloc_degenerate_sizes_are_no_ops():
+    assert _noalloc(m=0) == nv.SPMM_OK
+    assert _noalloc(n=0, ld=1) == nv.SPMM_OK
+
+
 def test_tune_cache_file_round_trip(tmp_path):
     """A loaded tune-cache entry is kept and written back unchanged; files that
     are missing, of another format or malformed are refused."""
