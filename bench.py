@@ -540,6 +540,7 @@ def rowblock_sweep():
                                                              k=2_097_152))]
     rb_shapes = [dict(kernel=nv.SPMM_KERNEL_ROWBLOCK, rows_per_block=R, lanes_per_row=l, unroll=u)
                  for R in (2, 4, 8) for l in (64, 32, 16, 8) for u in (2, 4)]
+    recs = []
     for desc, make in mats:
         A = make()
         rows = np.repeat(np.arange(A.m, dtype=np.int64) // 4, A.row_lengths())
@@ -568,10 +569,12 @@ def rowblock_sweep():
                    "rowblock_ms": round(rb[0], 4), "rowblock_shape": rb[1],
                    "fastest": best[1]}
             print(json.dumps(rec), flush=True)
+            recs.append(rec)
             del Bt, C
             torch.cuda.empty_cache()
         del rp, ci, vals, A
         torch.cuda.empty_cache()
+    return recs
 
 
 def heuristic_sweep(n=64):
@@ -667,7 +670,7 @@ def heuristic_sweep(n=64):
                   for r in recs)
         return round(sum(ok) / len(ok), 3), round(float(np.exp(tot / len(recs))), 3)
     mi_acc, mi_loss = rule_stats("mi355x_rule")
-    print(json.dumps({"summary": "heuristic sweep", "n": n, "matrices": len(recs),
+    summary = {"summary": "heuristic sweep", "n": n, "matrices": len(recs),
                       "mi355x_rule": "merge if mean < 4 or longest row >= 4096; else row blocks "
                                      "of 2 if n >= 32 and pairs of rows hold <= 0.9 distinct "
                                      "columns per entry; else row split",
@@ -675,7 +678,9 @@ def heuristic_sweep(n=64):
                       "paper_threshold": 9.35, "paper_rule_accuracy": round(acc(9.35), 3),
                       "paper_rule_geomean_slowdown": round(loss(9.35), 3),
                       "best_threshold": best_th, "best_threshold_accuracy": round(acc(best_th), 3),
-                      "best_threshold_geomean_slowdown": round(loss(best_th), 3)}), flush=True)
+                      "best_threshold_geomean_slowdown": round(loss(best_th), 3)}
+    print(json.dumps(summary), flush=True)
+    return recs + [summary]
 
 
 def nz_compare(n=64):
@@ -695,6 +700,7 @@ def nz_compare(n=64):
              ("power law, no empty rows", None), ("power law on 10% of rows, rest empty", 0.10),
              ("power law on 1% of rows, rest empty", 0.01),
              ("900k empty rows, then 100k rows of 160", "run")]
+    recs = []
     for desc, frac in cases:
         if frac is None:
             A = wl.power_law(seed=1002)
@@ -729,8 +735,10 @@ def nz_compare(n=64):
         rec["autotune_kernel"] = nv.KERNEL_NAMES[plan.info().config.kernel]
         plan.close()
         print(json.dumps(rec), flush=True)
+        recs.append(rec)
         del rp, ci, vals, Bt, C
         torch.cuda.empty_cache()
+    return recs
 
 
 def table_size_sweep(n=64):
@@ -748,6 +756,7 @@ def table_size_sweep(n=64):
     rp = torch.from_numpy(wl.rowptr_from_lengths(lengths)).cuda()
     nnz = int(lengths.sum())
     C = torch.empty(M, n, device="cuda")
+    recs = []
     for k in (1_000_000, 500_000, 250_000, 64_000, 16_000):
         ci = torch.from_numpy(wl.distinct_sorted_columns(rng, lengths, k)).cuda()
         vals = torch.rand(nnz, device="cuda")
@@ -759,32 +768,52 @@ def table_size_sweep(n=64):
             rec[name] = round(ms, 4)
         rec["gather_TBs"] = round(nnz * n * 4 / (min(rec["merge_ms"], rec["nzsplit_ms"]) * 1e-3) / 1e12, 2)
         print(json.dumps(rec), flush=True)
+        recs.append(rec)
         del ci, vals, B
         torch.cuda.empty_cache()
+    return recs
 
 
-def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1)):
+def column_panels(rp, ci, vals, m, k, P):
+    """Split A (rows with sorted columns) into P column panels of k / P
+    columns: per panel the CSR of the entries whose column falls in it, with
+    columns counted from the panel's first (the Greiner-Jacob 2-D tiling with
+    one row tile). Built with torch on the device; returns [(rowptr, colind,
+    vals, lo, hi)]."""
+    import torch
+    out = []
+    rows = torch.repeat_interleave(torch.arange(m, device="cuda"),
+                                   (rp[1:] - rp[:-1]).long())
+    for p in range(P):
+        lo, hi = p * k // P, (p + 1) * k // P
+        sel = (ci >= lo) & (ci < hi)
+        cnt = torch.bincount(rows[sel], minlength=m)
+        rpp = torch.zeros(m + 1, dtype=torch.int64, device="cuda")
+        rpp[1:] = torch.cumsum(cnt, 0)
+        out.append((rpp.to(torch.int32), (ci[sel] - lo).to(torch.int32), vals[sel], lo, hi))
+        del sel, cnt
+    del rows
+    return out
+
+
+def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1), panels=(4, 8, 16)):
     """Sparse versus dense (Fig. 7): a 100k x 100k matrix with a fixed share
     of distinct random columns in every row times a 100k x 64 B, SpMM (plan by
     timing) against the dense product of the same matrix stored densely
-    (torch.mm, i.e. the vendor BLAS), in float32 and bfloat16."""
+    (torch.mm, i.e. the vendor BLAS), in float32 and bfloat16. From 1 %
+    density on, also the 2-D tiling question of Sec. 6: A cut into P column
+    panels, each panel's product planned by timing, summed (float32); B's
+    panel slice then fits one XCD's L2."""
     import torch
     from paper_1803_08601_amd import native as nv
+    from paper_1803_08601_amd import workloads as wl
     N = 100_000
-    g = torch.Generator(device="cuda")
-    g.manual_seed(11)
+    recs = []
     for rho in densities:
-        L = max(1, int(round(rho * N)))
-        cols = []
-        for r0 in range(0, N, 1000):  # L distinct columns per row: the L smallest of N keys
-            keys = torch.rand(min(1000, N - r0), N, generator=g, device="cuda")
-            cols.append(torch.topk(keys, L, dim=1, largest=False).indices.sort(dim=1).values.to(torch.int32))
-            del keys
-        ci = torch.cat(cols).reshape(-1)
-        del cols
-        rp = torch.arange(0, (N + 1) * L, L, dtype=torch.int64, device="cuda").to(torch.int32)
+        rp, ci, vals, L = wl.fixed_density_device(11, N, rho)
         nnz = N * L
-        vals = torch.rand(nnz, generator=g, device="cuda") - 0.5
+        g = torch.Generator(device="cuda")
+        g.manual_seed(12)
         Bt = torch.rand(N, n, generator=g, device="cuda") - 0.5
         C = torch.empty(N, n, device="cuda")
         rec = {"density": rho, "nnz": nnz, "n": n}
@@ -792,6 +821,7 @@ def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1)):
             v, b = vals.to(dt), Bt.to(dt)
             plan = nv.Plan(rp, ci, N, N, n, dtype=nv.dtype_code(dt), mode="autotune", nnz=nnz)
             rec[f"spmm_{name}_ms"] = round(_timed(lambda: plan.execute(v, b, C), 10, 2), 4)
+            rec[f"spmm_{name}_kernel"] = nv.KERNEL_NAMES[plan.info().config.kernel]
             plan.close()
             D = torch.zeros(N, N, dtype=dt, device="cuda")
             rows = torch.arange(N, device="cuda").repeat_interleave(L)
@@ -800,9 +830,31 @@ def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1)):
             rec[f"dense_{name}_ms"] = round(_timed(lambda: torch.mm(D, b), 5, 1), 4)
             del D
             torch.cuda.empty_cache()
+        if rho >= 0.01:
+            for P in panels:
+                parts = column_panels(rp, ci, vals, N, N, P)
+                Cp = torch.empty(P, N, n, device="cuda")
+                plans = [nv.Plan(prp, pci, N, hi - lo, n, nnz=int(pci.numel()), mode="autotune")
+                         for prp, pci, _, lo, hi in parts]
+
+                def products():
+                    for q, (pl, (_, _, pv, lo, hi)) in enumerate(zip(plans, parts)):
+                        pl.execute(pv, Bt[lo:hi], Cp[q])
+
+                def tiled():
+                    products()
+                    torch.sum(Cp, 0, out=C)
+                rec[f"panels{P}_f32_ms"] = round(_timed(tiled, 10, 2), 4)
+                rec[f"panels{P}_products_ms"] = round(_timed(products, 10, 2), 4)
+                for pl in plans:
+                    pl.close()
+                del parts, Cp, plans
+                torch.cuda.empty_cache()
         print(json.dumps(rec), flush=True)
-        del ci, rp, vals, Bt, C
+        recs.append(rec)
+        del rp, ci, vals, Bt, C
         torch.cuda.empty_cache()
+    return recs
 
 
 def host_cpu():
@@ -958,6 +1010,7 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
         fetch = read_counter_csv(os.path.join(rdir, "fetch"))
         write = read_counter_csv(os.path.join(rdir, "write"))
         l2 = read_counter_csv(os.path.join(rdir, "l2"))
+        l2_names = " ".join(sorted({c for _, cs in l2 for c in cs}))
         stats = read_kernel_stats(os.path.join(rdir, "trace"))
         for m in json.load(open(mf)):
             k = m["steps"]
@@ -995,7 +1048,7 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
                    "kernel_ms_cold_mean": m["kernel_ms_cold_mean"], "profile": fam[0]}
             lst = [r for r in records.get(m["row"], []) if r.get("config") != m["config"]]
             records[m["row"]] = [rec] + lst
-            rows.append((fam, m, rec, per, args, stats))
+            rows.append((fam, m, rec, per, (args, l2_names), stats))
     with open(path, "w") as fh:
         json.dump(records, fh, indent=1, sort_keys=True)
         fh.write("\n")
@@ -1011,7 +1064,7 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
              "between the L2 caches and the fabric, so it includes Infinity Cache hits. Bytes_min: "
              "A, B and C moved once; gather model: every entry fetching its B row.", "",
              "Commands (repository root):", "", "```"]
-        for a_ in sorted({r[4] for r in mine}):
+        for a_, l2n in sorted({r[4] for r in mine}):
             tc = "--tune-cache <run>/<row>/tune.txt"
             L += [f"{rp} --kernel-trace --stats --output-format csv -d <run>/<row>/trace -o r -- "
                   f"python3 bench.py {a_} {tc} --manifest <run>/<row>/manifest.json",
@@ -1019,7 +1072,7 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
                   f"python3 bench.py {a_} {tc} --manifest <run>/<row>/fetch.manifest.json",
                   f"{rp} --pmc WRITE_SIZE --output-format csv -d <run>/<row>/write -o r -- "
                   f"python3 bench.py {a_} {tc} --manifest <run>/<row>/write.manifest.json",
-                  f"{rp} --pmc TCC_HIT_sum TCC_MISS_sum TA_TA_BUSY_sum GRBM_GUI_ACTIVE "
+                  f"{rp} --pmc {l2n} "
                   f"--output-format csv -d <run>/<row>/l2 -o r -- python3 bench.py {a_} {tc} "
                   f"--manifest <run>/<row>/l2.manifest.json"]
         L += [f"{rp} --pmc FETCH_SIZE --output-format csv -d <run>/copy/fetch -o c -- "
@@ -1051,6 +1104,30 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
         with open(os.path.join(profiles, fam[0]), "w") as fh:
             fh.write("\n".join(L) + "\n")
     return records
+
+
+def write_summary(path, title, about, recs):
+    """Markdown record of a sweep: what it measures, the command that made
+    it (this process's arguments, run from the repository root on one
+    MI355X) and one table row per record (nested values as JSON)."""
+    keys = []
+    for r in recs:
+        for k_ in r:
+            if k_ not in keys:
+                keys.append(k_)
+
+    def cell(v):
+        if isinstance(v, (dict, list)):
+            return "`" + json.dumps(v, separators=(",", ":")) + "`"
+        return "" if v is None else str(v)
+    args = [a for a in sys.argv[1:]]
+    L = [f"# {title}", "", about, "", "Command (repository root, one MI355X):", "", "```",
+         "python3 bench.py " + " ".join(args), "```", "",
+         "| " + " | ".join(keys) + " |", "|" + "---|" * len(keys)]
+    for r in recs:
+        L.append("| " + " | ".join(cell(r.get(k_)) for k_ in keys) + " |")
+    with open(path, "w") as fh:
+        fh.write("\n".join(L) + "\n")
 
 
 ROWS = ["plain-n32-f32", "powerlaw-n8-f32", "powerlaw-n64-bf16", "stencil-n16-f32",
@@ -1094,6 +1171,8 @@ def main():
                     help="sparse versus dense product over density (100k x 100k, n = 64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summary", default=None, metavar="FILE",
+                    help="with a sweep mode: also write its records as a markdown table")
     ap.add_argument("--tune-cache", default=None, metavar="FILE",
                     help="load the autotuner's choices from FILE if it exists and save them "
                          "there at exit (profiling passes then plan the shapes the traced "
@@ -1123,8 +1202,13 @@ def main():
             with open(args.manifest, "w") as fh:
                 json.dump(manifest, fh, indent=1)
 
+    def summarise(recs, title, about):
+        if args.summary:
+            write_summary(args.summary, title, about, recs)
+
     if args.sweep:
-        heuristic_sweep(args.n)
+        summarise(heuristic_sweep(args.n), "Kernel choice over row-length regimes (Sec. 5.4)",
+                  heuristic_sweep.__doc__.strip().replace("\n    ", " "))
         return
     records = load_counters()
     if args.row:
@@ -1139,16 +1223,20 @@ def main():
         print(json.dumps(rec), flush=True)
         return
     if args.crossover:
-        crossover(args.n)
+        summarise(crossover(args.n), "Sparse versus dense, and column panels (Fig. 7, Sec. 6)",
+                  crossover.__doc__.strip().replace("\n    ", " "))
         return
     if args.nzsplit:
-        nz_compare(args.n)
+        summarise(nz_compare(args.n), "Nonzero split against the merge-path split",
+                  nz_compare.__doc__.strip().replace("\n    ", " "))
         return
     if args.rowblock_sweep:
-        rowblock_sweep()
+        summarise(rowblock_sweep(), "Row blocks against row split and merge path",
+                  rowblock_sweep.__doc__.strip().replace("\n    ", " "))
         return
     if args.table_size_sweep:
-        table_size_sweep(args.n)
+        summarise(table_size_sweep(args.n), "Gather rate against the size of B",
+                  table_size_sweep.__doc__.strip().replace("\n    ", " "))
         return
     if args.copy_calibration:
         a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")

@@ -316,6 +316,30 @@ def random_csr(seed, m, k, density=0.1, empty_frac=0.0, values="uniform",
     return CSR(rowptr, colind, vals, m, k)
 
 
+def fixed_density_device(seed, N, density, chunk=1000):
+    """Square N x N matrix with L = max(1, round(density * N)) distinct
+    uniformly random columns in every row (sorted), values U[-0.5, 0.5) -
+    the sparse operand of the sparse-versus-dense comparison (Fig. 7). Built
+    on the current GPU with a seeded torch generator (at 10 % of 100k x 100k
+    it holds 1e9 entries); the same seed gives the same matrix. Returns
+    (rowptr, colind, vals) as int32 / int32 / float32 device tensors and L."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    L = max(1, int(round(density * N)))
+    parts = []
+    for r0 in range(0, N, chunk):  # the L smallest of N random keys per row
+        keys = torch.rand(min(chunk, N - r0), N, generator=g, device="cuda")
+        parts.append(torch.topk(keys, L, dim=1, largest=False).indices.sort(dim=1).values
+                     .to(torch.int32))
+        del keys
+    colind = torch.cat(parts).reshape(-1)
+    del parts
+    rowptr = torch.arange(0, (N + 1) * L, L, dtype=torch.int64, device="cuda").to(torch.int32)
+    vals = torch.rand(N * L, generator=g, device="cuda") - 0.5
+    return rowptr, colind, vals, L
+
+
 def _values(rng, size, kind):
     if kind == "uniform":
         return uniform(rng, size)

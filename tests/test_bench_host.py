@@ -145,3 +145,14 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert not r.stdout.strip()
+
+
+def test_write_summary_table(tmp_path):
+    """Sweep records become one markdown table (nested values as JSON) under
+    the command that made them."""
+    f = tmp_path / "s.md"
+    bench.write_summary(str(f), "T", "about", [{"a": 1, "b": {"x": 2}}, {"a": 3, "c": None}])
+    text = f.read_text().splitlines()
+    assert text[0] == "# T" and text[7].startswith("python3 bench.py")
+    assert "| a | b | c |" in text
+    assert '| 1 | `{"x":2}` |  |' in text and "| 3 |  |  |" in text
