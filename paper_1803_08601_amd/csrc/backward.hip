@@ -384,8 +384,9 @@ hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int
 // row among the staged row ends. For U entries at a time a slot gathers the
 // B row chunks, forms the partial dot products with the dC row chunk (kept
 // in registers while the row lasts when the row fits one column tile), and
-// sums its lanes with DPP row exchanges; lane 0 writes dvals. No entry
-// depends on another, so there is no carry-out.
+// sums its lanes with DPP row exchanges; the wavefront then writes the step's
+// consecutive dvals with one store (lane g of a slot writing its g-th sum).
+// No entry depends on another, so there is no carry-out.
 template <class S, int VEC, int U, bool ONE_TILE>
 __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr,
                                                    const int* __restrict__ colind,
@@ -500,10 +501,22 @@ __global__ __launch_bounds__(kBlock) void k_sddmm(const int* __restrict__ rowptr
             }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            part[u] = group_sum(part[u], g_log2);
-            if (g == 0 && jb + u * SPW < je)
-                __builtin_nontemporal_store(part[u], dvals + j0 + jb + u * SPW);
+        for (int u = 0; u < U; ++u) part[u] = group_sum(part[u], g_log2);
+        if ((1 << g_log2) >= U) {
+            // Every lane of a slot holds its U sums: lane g < U writes the
+            // g-th (entry jb + g SPW), so one store covers the wavefront's
+            // SPW * U consecutive entries of this step.
+            float out = part[0];
+#pragma unroll
+            for (int u = 1; u < U; ++u)
+                if (g == u) out = part[u];
+            const int j = jb + g * SPW;
+            if (g < U && j < je) __builtin_nontemporal_store(out, dvals + j0 + j);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (g == 0 && jb + u * SPW < je)
+                    __builtin_nontemporal_store(part[u], dvals + j0 + jb + u * SPW);
         }
     }
 }
