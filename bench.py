@@ -774,36 +774,15 @@ def table_size_sweep(n=64):
     return recs
 
 
-def column_panels(rp, ci, vals, m, k, P):
-    """Split A (rows with sorted columns) into P column panels of k / P
-    columns: per panel the CSR of the entries whose column falls in it, with
-    columns counted from the panel's first (the Greiner-Jacob 2-D tiling with
-    one row tile). Built with torch on the device; returns [(rowptr, colind,
-    vals, lo, hi)]."""
-    import torch
-    out = []
-    rows = torch.repeat_interleave(torch.arange(m, device="cuda"),
-                                   (rp[1:] - rp[:-1]).long())
-    for p in range(P):
-        lo, hi = p * k // P, (p + 1) * k // P
-        sel = (ci >= lo) & (ci < hi)
-        cnt = torch.bincount(rows[sel], minlength=m)
-        rpp = torch.zeros(m + 1, dtype=torch.int64, device="cuda")
-        rpp[1:] = torch.cumsum(cnt, 0)
-        out.append((rpp.to(torch.int32), (ci[sel] - lo).to(torch.int32), vals[sel], lo, hi))
-        del sel, cnt
-    del rows
-    return out
-
-
 def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1), panels=(4, 8, 16)):
     """Sparse versus dense (Fig. 7): a 100k x 100k matrix with a fixed share
     of distinct random columns in every row times a 100k x 64 B, SpMM (plan by
-    timing) against the dense product of the same matrix stored densely
-    (torch.mm, i.e. the vendor BLAS), in float32 and bfloat16. From 1 %
-    density on, also the 2-D tiling question of Sec. 6: A cut into P column
-    panels, each panel's product planned by timing, summed (float32); B's
-    panel slice then fits one XCD's L2."""
+    timing, whose candidates include column panels) against the dense product
+    of the same matrix stored densely (torch.mm, i.e. the vendor BLAS), in
+    float32 and bfloat16. From 1 % density on, also the 2-D tiling question
+    of Sec. 6 directly: row split without panels against P column panels
+    (float32, one row-split pass per panel adding into C), B's panel slice
+    then fitting one XCD's L2."""
     import torch
     from paper_1803_08601_amd import native as nv
     from paper_1803_08601_amd import workloads as wl
@@ -822,6 +801,7 @@ def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1), pan
             plan = nv.Plan(rp, ci, N, N, n, dtype=nv.dtype_code(dt), mode="autotune", nnz=nnz)
             rec[f"spmm_{name}_ms"] = round(_timed(lambda: plan.execute(v, b, C), 10, 2), 4)
             rec[f"spmm_{name}_kernel"] = nv.KERNEL_NAMES[plan.info().config.kernel]
+            rec[f"spmm_{name}_panels"] = plan.info().config.col_panels
             plan.close()
             D = torch.zeros(N, N, dtype=dt, device="cuda")
             rows = torch.arange(N, device="cuda").repeat_interleave(L)
@@ -831,25 +811,22 @@ def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1), pan
             del D
             torch.cuda.empty_cache()
         if rho >= 0.01:
-            for P in panels:
-                parts = column_panels(rp, ci, vals, N, N, P)
-                Cp = torch.empty(P, N, n, device="cuda")
-                plans = [nv.Plan(prp, pci, N, hi - lo, n, nnz=int(pci.numel()), mode="autotune")
-                         for prp, pci, _, lo, hi in parts]
-
-                def products():
-                    for q, (pl, (_, _, pv, lo, hi)) in enumerate(zip(plans, parts)):
-                        pl.execute(pv, Bt[lo:hi], Cp[q])
-
-                def tiled():
-                    products()
-                    torch.sum(Cp, 0, out=C)
-                rec[f"panels{P}_f32_ms"] = round(_timed(tiled, 10, 2), 4)
-                rec[f"panels{P}_products_ms"] = round(_timed(products, 10, 2), 4)
-                for pl in plans:
-                    pl.close()
-                del parts, Cp, plans
-                torch.cuda.empty_cache()
+            # the best row split without panels (whole and half-width column
+            # tiles) against each panel count
+            for P in (1,) + tuple(panels):
+                best = None
+                shapes = [(lpr, u, tc) for lpr in (64, 32, 16) for u in (2, 4, 8)
+                          for tc in (0, n // 2)] if P == 1 else \
+                    [(lpr, u, 0) for lpr in (64, 32) for u in (2, 4, 8)]
+                for lpr, u, tc in shapes:
+                    cfg = dict(kernel=nv.SPMM_KERNEL_ROWSPLIT, lanes_per_row=lpr, unroll=u,
+                               tile_cols=tc, col_panels=P)
+                    plan = nv.Plan(rp, ci, N, N, n, nnz=nnz, config=cfg)
+                    ms = _timed(lambda: plan.execute(vals, Bt, C), 10, 2)
+                    plan.close()
+                    best = ms if best is None else min(best, ms)
+                rec["rowsplit_f32_ms" if P == 1 else f"panels{P}_f32_ms"] = round(best, 4)
+            torch.cuda.empty_cache()
         print(json.dumps(rec), flush=True)
         recs.append(rec)
         del rp, ci, vals, Bt, C

@@ -67,7 +67,10 @@ typedef enum spmm_dtype { SPMM_F32 = 0, SPMM_BF16 = 1, SPMM_F16 = 2 } spmm_dtype
  *              nnz / m < 9.35, row split otherwise (compared exactly as
  *              100 * nnz < 935 * m).
  *   AUTOTUNE : time the candidate kernels and shapes on scratch buffers of
- *              the plan's sizes and keep the fastest.
+ *              the plan's sizes and keep the fastest. Column panels
+ *              (spmm_config.col_panels) are candidates when the rows are
+ *              sorted, B is larger than 4 MB and rows hold 64 or more entries
+ *              on average.
  *   ROWSPLIT / MERGE : force that kernel with default shapes.
  *   RULE     : the rule re-derived on MI355X from the kernel-choice
  *              sweep (the Sec. 5.4 procedure on this GPU): merge-based when
@@ -156,6 +159,16 @@ typedef struct spmm_config {
                               through every plane before the next strip, so each B row is
                               reused from L2 by the three planes that need it. Only the order
                               of the workgroups changes: results are bitwise the same. */
+    int32_t col_panels;    /* ROWSPLIT: 0 or 1 = none; P = 2 .. 64 = column panels (the 2-D
+                              tiling Sec. 6 discusses, with one row tile): A's columns are cut
+                              into P panels of ceil(k / P) columns and the product runs as P
+                              row-split passes, pass p taking from every row the entries whose
+                              column lies in panel p and adding their sum into C (pass 0
+                              overwrites C), so each pass gathers from a slice of B that can
+                              stay in an XCD's L2. The plan stores each row's panel starts
+                              ((P + 1) * m ints). Needs column indices that strictly increase
+                              in every row (SPMM_ERR_UNSUPPORTED otherwise). Each element of C
+                              is summed panel by panel: a different order from P = 1. */
 } spmm_config;
 
 typedef struct spmm_plan_info {
@@ -258,9 +271,11 @@ int spmm_cache_clear(void);
 /* Autotuner results kept across processes. The autotuner remembers, per
  * process, the shape it chose for each key (device, m, k, nnz, n, ld,
  * longest row, rows of >= 1024 entries, dtype, unroll, largest merge piece,
- * row blocks allowed); a plan with a known key takes that shape without
- * timing trials. spmm_tune_cache_save writes every remembered choice to the
- * text file path_host; spmm_tune_cache_load adds a file's choices (a later
+ * row blocks allowed, column panels allowed); a plan with a known key takes
+ * that shape without timing trials. spmm_tune_cache_save writes every
+ * remembered choice to the text file path_host (format version 2: a header
+ * line, then one line per key - 13 key fields, the 9 fields of spmm_config,
+ * the tuned time in ms); spmm_tune_cache_load adds a file's choices (a later
  * entry for one key replaces an earlier one). A loaded shape is checked like
  * a forced config when a plan would use it and ignored (tuned afresh) if it
  * does not fit. Returns SPMM_ERR_INVALID for an unreadable, unwritable or

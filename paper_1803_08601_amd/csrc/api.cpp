@@ -134,6 +134,24 @@ int forward(const spmm_plan_s& p, const int* rowptr, const int* colind, const vo
         if (e != hipSuccess) return hip_fail(e, "row-block launch");
         return SPMM_OK;
     }
+    if (p.cfg.kernel == SPMM_KERNEL_ROWSPLIT && p.cfg.col_panels >= 2) {
+        // one row-split pass per column panel, each adding into C after the first
+        if (!p.cp.starts || p.cp.P != p.cfg.col_panels)
+            return fail(SPMM_ERR_STATE, "column-panel plan without its panel starts");
+        for (int q = 0; q < p.cp.P; ++q) {
+            spmmk::ForwardArgs aq = a;
+            aq.rowptr = p.cp.starts + (int64_t)q * p.m;
+            aq.rowend = p.cp.starts + (int64_t)(q + 1) * p.m;
+            aq.accumulate = q > 0;
+            const hipError_t e =
+                semiring == SPMM_PLUS_TIMES
+                    ? spmmk::launch_forward_plus_times(p.dtype, false, s, aq, st,
+                                                       q == p.cp.P - 1 ? ev_after : nullptr)
+                    : spmmk::launch_forward_semiring(semiring, p.dtype, false, s, aq, st);
+            if (e != hipSuccess) return hip_fail(e, "column-panel launch");
+        }
+        return SPMM_OK;
+    }
     // (other semirings on a row-block plan run row split with its lane shape)
     const hipError_t e =
         semiring == SPMM_PLUS_TIMES
@@ -175,6 +193,26 @@ static int prepare_merge(const spmm_plan_s& p, MergeWs& ws, int W, bool nz, hipS
     hipError_t e = spmmk::launch_merge_partition(p.rowptr, p.m, p.nnz, W, P, nz ? 1 : 0,
                                                  ws.coords, st);
     if (e != hipSuccess) return hip_fail(e, "merge partition launch");
+    return SPMM_OK;
+}
+
+static void free_cp(ColPanels& cp) {
+    if (cp.starts) (void)hipFree(cp.starts);
+    cp = ColPanels{};
+}
+
+// Panel starts of P column panels of ceil(k / P) columns each.
+static int prepare_panels(const spmm_plan_s& p, ColPanels& cp, int P, hipStream_t st) {
+    if (cp.starts && cp.P == P) return SPMM_OK;
+    free_cp(cp);
+    const int64_t width = (p.k + P - 1) / P;
+    SPMM_HIP(hipMalloc(&cp.starts, sizeof(int) * std::max<int64_t>(1, (int64_t)(P + 1) * p.m)));
+    const hipError_t e = spmmk::launch_panel_starts(p.rowptr, p.colind, p.m, P, width, cp.starts, st);
+    if (e != hipSuccess) {
+        free_cp(cp);
+        return hip_fail(e, "panel starts");
+    }
+    cp.P = P;
     return SPMM_OK;
 }
 
@@ -269,6 +307,13 @@ static int find_planes(spmm_plan_s& p, hipStream_t st) {
     return SPMM_OK;
 }
 
+// Column panels: at most kMaxPanels; autotuner candidates when the rows hold
+// kPanelMinMean entries or more on average and B is larger than an L2, with
+// panels whose B slice is about kPanelBytes.
+constexpr int kMaxPanels = 64;
+constexpr double kPanelMinMean = 64.0;
+constexpr int64_t kPanelBytes = int64_t(2) << 20;
+
 // Distinct columns per entry of blocks of 2 rows at or below which row blocks
 // are worth trying (mode RULE also needs n >= kRuleMinN).
 constexpr double kRuleUnionRatio = 0.9;
@@ -296,6 +341,17 @@ static int check_config(const spmm_plan_s& p, spmm_config& c) {
     }
     if (c.tile_order < 0 || c.tile_order > 2)
         return fail(SPMM_ERR_INVALID, "config.tile_order %d: use 0, 1 or 2", c.tile_order);
+    if (c.col_panels == 1) c.col_panels = 0;
+    if (c.col_panels != 0) {
+        if (c.kernel != SPMM_KERNEL_ROWSPLIT)
+            return fail(SPMM_ERR_UNSUPPORTED, "config.col_panels needs the row-split kernel");
+        if (c.col_panels < 2 || c.col_panels > kMaxPanels)
+            return fail(SPMM_ERR_UNSUPPORTED, "config.col_panels %d: use 0 .. %d", c.col_panels,
+                        kMaxPanels);
+        if (p.sorted != 1)
+            return fail(SPMM_ERR_UNSUPPORTED,
+                        "column panels need strictly increasing column indices in every row");
+    }
     if (c.vec == 0) c.vec = can16 ? v16 : 1;
     if (c.vec != 1 && c.vec != v16)
         return fail(SPMM_ERR_UNSUPPORTED, "config.vec %d: use 1 or %d for this dtype", c.vec, v16);
@@ -351,18 +407,19 @@ struct TuneKey {
     int device;
     int64_t m, k, nnz, n, ld, maxrow, longrows;
     int dtype, unroll, max_W;
-    bool rowblock;
+    bool rowblock, panels;
     bool operator<(const TuneKey& o) const {
         return std::tie(device, m, k, nnz, n, ld, maxrow, longrows, dtype, unroll, max_W,
-                        rowblock) <
+                        rowblock, panels) <
                std::tie(o.device, o.m, o.k, o.nnz, o.n, o.ld, o.maxrow, o.longrows, o.dtype,
-                        o.unroll, o.max_W, o.rowblock);
+                        o.unroll, o.max_W, o.rowblock, o.panels);
     }
 };
 static std::map<TuneKey, std::pair<spmm_config, double>> g_tuned;
 
 static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_unroll,
-                                                int max_W, bool rowblock) {
+                                                int max_W, bool rowblock,
+                                                const std::vector<int>& panels) {
     std::vector<spmm_config> out;
     const int v16 = vec16(p.dtype);
     const int vec = (p.n % v16 == 0 && p.ld % v16 == 0) ? v16 : 1;
@@ -410,6 +467,16 @@ static std::vector<spmm_config> tune_candidates(const spmm_plan_s& p, int fixed_
                     for (int u : unrolls)
                         out.push_back({SPMM_KERNEL_ROWBLOCK, vec, lpr, u, 1024, tc, R});
             }
+    // Column panels (long sorted rows, B larger than an L2): row split with
+    // whole or half wavefronts per row, one pass per panel.
+    for (int P : panels) {
+        int g_log2, nt;
+        slot_geometry(p.n, vec, &g_log2, &nt, 0);
+        for (int lpr : {spmmk::kWaveSize, spmmk::kWaveSize / 2})
+            if (lpr >= (1 << g_log2))
+                for (int u : unrolls)
+                    out.push_back({SPMM_KERNEL_ROWSPLIT, vec, lpr, u, 1024, 0, 0, 0, P});
+    }
     return out;
 }
 
@@ -418,7 +485,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     const int max_W = opts ? opts->max_W : 0;
     const bool own = opts && opts->C && (p.nnz == 0 || (opts->vals && opts->B));
     const TuneKey key{p.device, p.m, p.k, p.nnz, p.n, p.ld, p.max_row_len, p.long_rows, p.dtype,
-                      fixed_unroll, max_W, !opts || opts->rowblock};
+                      fixed_unroll, max_W, !opts || opts->rowblock, !opts || opts->panels};
     {
         std::pair<spmm_config, double> hit{};
         bool found = false;
@@ -432,7 +499,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
         }
         // A cached row-block choice holds only for a matrix with sorted rows
         // (the key does not see the order of columns): else tune afresh.
-        if (found && hit.first.kernel == SPMM_KERNEL_ROWBLOCK) {
+        if (found && (hit.first.kernel == SPMM_KERNEL_ROWBLOCK || hit.first.col_panels >= 2)) {
             const int rc0 = ensure_sorted(p, st);
             if (rc0 != SPMM_OK) return rc0;
             found = p.sorted == 1;
@@ -460,6 +527,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     float* use_C = own ? opts->C : nullptr;
     MergeWs ws;
     RowBlocks rb2, rb4;  // row-block structures of the candidates
+    std::map<int, ColPanels> cps;  // panel starts of the column-panel candidates
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = SPMM_OK;
     auto cleanup = [&]() {
@@ -469,6 +537,7 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
         free_ws(ws);
         free_rb(rb2);
         free_rb(rb4);
+        for (auto& kv : cps) free_cp(kv.second);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
@@ -511,6 +580,22 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
         if (!rowblock) free_rb(rb2);
     }
 
+    // Column panels for long sorted rows when B does not fit an L2: about
+    // kPanelBytes of B per panel (P0, a power of two), and half and twice that.
+    std::vector<int> panels;
+    const int64_t b_bytes = p.k * p.ld * elem_bytes(p.dtype);
+    const double mean = p.m ? double(p.nnz) / double(p.m) : 0.0;
+    if ((!opts || opts->panels) && p.nnz > 0 && mean >= kPanelMinMean && b_bytes > kL2Bytes) {
+        rc = ensure_sorted(p, st);
+        if (rc != SPMM_OK) { cleanup(); return rc; }
+        if (p.sorted == 1) {
+            int P0 = 2;
+            while (P0 < kMaxPanels && int64_t(P0) * kPanelBytes < b_bytes) P0 *= 2;
+            for (int P : {P0 / 2, P0, P0 * 2})
+                if (P >= 2 && P <= kMaxPanels && mean >= 4.0 * P) panels.push_back(P);
+        }
+    }
+
     // Candidates within kTie (1.5 %, above the run-to-run spread of the
     // median) of the fastest count as equal; the earliest in
     // candidate order wins, so repeated tuning of one matrix picks one shape.
@@ -518,11 +603,12 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
     double best = 1e30;
     std::vector<std::pair<spmm_config, double>> timed;
     int slow_rowsplit = 0;
-    for (spmm_config c : tune_candidates(p, fixed_unroll, max_W, rowblock)) {
+    for (spmm_config c : tune_candidates(p, fixed_unroll, max_W, rowblock, panels)) {
         if (c.kernel == SPMM_KERNEL_ROWSPLIT && slow_rowsplit >= 3) continue;
         spmm_plan_s q = p;  // shallow copy: never destroyed
         q.ws = MergeWs{};
         q.rb = RowBlocks{};
+        q.cp = ColPanels{};
         if (check_config(q, c) != SPMM_OK) continue;
         q.cfg = c;
         if (is_merge(c.kernel)) {
@@ -535,6 +621,11 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
             rc = prepare_rowblock(p, rb, c.rows_per_block, st);
             if (rc != SPMM_OK) { cleanup(); return rc; }
             q.rb = rb;
+        }
+        if (c.col_panels >= 2) {
+            rc = prepare_panels(p, cps[c.col_panels], c.col_panels, st);
+            if (rc != SPMM_OK) { cleanup(); return rc; }
+            q.cp = cps[c.col_panels];
         }
         std::vector<float> times;
         for (int rep = 0; rep < 6; ++rep) {
@@ -573,6 +664,11 @@ static int autotune(spmm_plan_s& p, hipStream_t st, const TuneOpts* opts) {
         free_rb(p.rb);
         p.rb = rb;
         rb = RowBlocks{};
+    }
+    if (best_cfg.col_panels >= 2 && best_ms < 1e30) {
+        free_cp(p.cp);
+        p.cp = cps[best_cfg.col_panels];
+        cps[best_cfg.col_panels] = ColPanels{};
     }
     cleanup();
 #undef TUNE_HIP
@@ -658,6 +754,7 @@ void destroy_plan(spmm_plan_s* p) {
     free_ws(p->ws);
     free_ws(p->sddmm_ws);
     free_rb(p->rb);
+    free_cp(p->cp);
     if (p->tr.at_rowptr) (void)hipFree(p->tr.at_rowptr);
     if (p->tr.at_colind) (void)hipFree(p->tr.at_colind);
     if (p->tr.perm) (void)hipFree(p->tr.perm);
@@ -701,7 +798,8 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
     } else {
         rc = row_stats(*p, st);
     }
-    const bool want_rowblock = forced ? forced->kernel == SPMM_KERNEL_ROWBLOCK
+    const bool want_rowblock = forced ? forced->kernel == SPMM_KERNEL_ROWBLOCK ||
+                                            forced->col_panels >= 2
                                       : mode == SPMM_MODE_ROWBLOCK;
     if (rc == SPMM_OK && want_rowblock) rc = ensure_sorted(*p, st);
     // plane structure for the tile order: looked for when B is larger than
@@ -742,6 +840,9 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
                            st);
     if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_ROWBLOCK && p->m > 0)
         rc = prepare_rowblock(*p, p->rb, p->cfg.rows_per_block, st);
+    if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_ROWSPLIT && p->cfg.col_panels >= 2 &&
+        p->m > 0)
+        rc = prepare_panels(*p, p->cp, p->cfg.col_panels, st);
     // SDDMM walks diagonal merge pieces (their row ends fit its LDS); other
     // plans get such a partition for it.
     if (rc == SPMM_OK && p->cfg.kernel != SPMM_KERNEL_MERGE && p->m > 0 && p->nnz > 0 &&
@@ -1157,15 +1258,18 @@ int spmm_tune_cache_save(const char* path_host) {
     }
     FILE* f = fopen(path_host, "w");
     if (!f) return fail(SPMM_ERR_INVALID, "cannot write %s", path_host);
-    fprintf(f, "spmm-tune-cache 1\n");
+    fprintf(f, "spmm-tune-cache 2\n");
     for (const auto& kv : all) {
         const TuneKey& k = kv.first;
         const spmm_config& c = kv.second.first;
-        fprintf(f, "%d %lld %lld %lld %lld %lld %lld %lld %d %d %d %d  %d %d %d %d %d %d %d %d  %.9g\n",
+        fprintf(f,
+                "%d %lld %lld %lld %lld %lld %lld %lld %d %d %d %d %d  %d %d %d %d %d %d %d %d %d"
+                "  %.9g\n",
                 k.device, (long long)k.m, (long long)k.k, (long long)k.nnz, (long long)k.n,
                 (long long)k.ld, (long long)k.maxrow, (long long)k.longrows, k.dtype, k.unroll,
-                k.max_W, k.rowblock ? 1 : 0, c.kernel, c.vec, c.lanes_per_row, c.unroll,
-                c.items_per_wg, c.tile_cols, c.rows_per_block, c.tile_order, kv.second.second);
+                k.max_W, k.rowblock ? 1 : 0, k.panels ? 1 : 0, c.kernel, c.vec, c.lanes_per_row,
+                c.unroll, c.items_per_wg, c.tile_cols, c.rows_per_block, c.tile_order,
+                c.col_panels, kv.second.second);
     }
     const bool ok = fclose(f) == 0;
     return ok ? SPMM_OK : fail(SPMM_ERR_INVALID, "cannot write %s", path_host);
@@ -1176,29 +1280,31 @@ int spmm_tune_cache_load(const char* path_host) {
     FILE* f = fopen(path_host, "r");
     if (!f) return fail(SPMM_ERR_INVALID, "cannot read %s", path_host);
     int version = 0;
-    if (fscanf(f, "spmm-tune-cache %d", &version) != 1 || version != 1) {
+    if (fscanf(f, "spmm-tune-cache %d", &version) != 1 || version != 2) {
         fclose(f);
-        return fail(SPMM_ERR_INVALID, "%s is not a version-1 tune cache", path_host);
+        return fail(SPMM_ERR_INVALID, "%s is not a version-2 tune cache", path_host);
     }
     std::vector<std::pair<TuneKey, std::pair<spmm_config, double>>> got;
     for (;;) {
         TuneKey k{};
         spmm_config c{};
         long long m, kk, nnz, n, ld, maxrow, longrows;
-        int rowblock = 0;
+        int rowblock = 0, panels = 0;
         double ms = 0.0;
-        const int r = fscanf(f, "%d %lld %lld %lld %lld %lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %lf",
+        const int r = fscanf(f,
+                             "%d %lld %lld %lld %lld %lld %lld %lld %d %d %d %d %d %d %d %d %d %d "
+                             "%d %d %d %d %lf",
                              &k.device, &m, &kk, &nnz, &n, &ld, &maxrow, &longrows, &k.dtype,
-                             &k.unroll, &k.max_W, &rowblock, &c.kernel, &c.vec, &c.lanes_per_row,
-                             &c.unroll, &c.items_per_wg, &c.tile_cols, &c.rows_per_block,
-                             &c.tile_order, &ms);
+                             &k.unroll, &k.max_W, &rowblock, &panels, &c.kernel, &c.vec,
+                             &c.lanes_per_row, &c.unroll, &c.items_per_wg, &c.tile_cols,
+                             &c.rows_per_block, &c.tile_order, &c.col_panels, &ms);
         if (r == EOF) break;
-        if (r != 21) {
+        if (r != 23) {
             fclose(f);
             return fail(SPMM_ERR_INVALID, "%s: malformed entry %zu", path_host, got.size() + 1);
         }
         k.m = m; k.k = kk; k.nnz = nnz; k.n = n; k.ld = ld; k.maxrow = maxrow;
-        k.longrows = longrows; k.rowblock = rowblock != 0;
+        k.longrows = longrows; k.rowblock = rowblock != 0; k.panels = panels != 0;
         got.push_back({k, {c, ms}});
     }
     fclose(f);

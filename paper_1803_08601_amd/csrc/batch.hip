@@ -64,11 +64,12 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchProb* __restrict__ 
         for (int t = w.first; t < w.first + w.count; ++t) {
             if (p.kernel == 0) {
                 if (p.vec == 1)
-                    rowsplit_block<S, 1, U>(p.rowptr, p.colind, vals, B, p.C, p.m, p.n, p.ld,
-                                            p.g_log2, p.ts_log2, t, w.coltile);
+                    rowsplit_block<S, 1, U>(p.rowptr, p.rowptr + 1, p.colind, vals, B, p.C, p.m,
+                                            p.n, p.ld, p.g_log2, p.ts_log2, t, w.coltile, false);
                 else
-                    rowsplit_block<S, S::kVec16, U>(p.rowptr, p.colind, vals, B, p.C, p.m, p.n,
-                                                    p.ld, p.g_log2, p.ts_log2, t, w.coltile);
+                    rowsplit_block<S, S::kVec16, U>(p.rowptr, p.rowptr + 1, p.colind, vals, B,
+                                                    p.C, p.m, p.n, p.ld, p.g_log2, p.ts_log2, t,
+                                                    w.coltile, false);
             } else {
                 if (p.vec == 1 && !p.nz)
                     merge_tile<S, 1, U>(p.rowptr, p.colind, vals, B, p.C, (int)p.m, p.n, p.ld,

@@ -35,7 +35,10 @@ hipError_t launch_offset_stats(const int* rowptr, const int* colind, int64_t m, 
                                hipStream_t st);
 
 // Operands of one forward product; coords, P and the carry arrays are the
-// merge-based workspace (unused by row split).
+// merge-based workspace (unused by row split). Row split takes row i's
+// entries from rowptr[i] to rowend[i] (rowend null: rowptr + 1, the whole
+// row) and, with accumulate set, adds its sums into C instead of writing
+// them (one pass of a column-panel product).
 struct ForwardArgs {
     const int* rowptr;
     const int* colind;
@@ -47,7 +50,15 @@ struct ForwardArgs {
     int64_t P;
     float* carry_vals;
     int* carry_rows;
+    const int* rowend;
+    int accumulate;
 };
+
+// Column panels: starts[p * m + i] = the first entry of row i whose column
+// is at least p * width (p = 0 .. P; row i's columns must not decrease), so
+// panel p of row i is entries starts[p * m + i] .. starts[(p + 1) * m + i].
+hipError_t launch_panel_starts(const int* rowptr, const int* colind, int64_t m, int P,
+                               int64_t width, int* starts, hipStream_t st);
 
 // The main kernel of one product and, for merge-based plans, its fix-up pass;
 // ev_after (may be null) is recorded between the two.

@@ -40,6 +40,12 @@ struct RowBlocks {
     int R = 0;
 };
 
+// Column panels of a row-split plan: (P + 1) * m panel starts.
+struct ColPanels {
+    int* starts = nullptr;
+    int P = 0;
+};
+
 struct Transpose {
     int* at_rowptr = nullptr;
     int* at_colind = nullptr;
@@ -61,6 +67,7 @@ struct spmm_plan_s {
     spmmh::MergeWs ws;
     spmmh::MergeWs sddmm_ws;  // merge partition for SDDMM when the kernel is row split
     spmmh::RowBlocks rb;      // ROWBLOCK plans
+    spmmh::ColPanels cp;      // row-split plans with column panels
     int sorted = -1;          // columns strictly increase in every row: 1 / 0 / -1 unknown
     // plane structure for the tile order of row split and row blocks (plane
     // distance and strip in rows, 0 when none was found)
@@ -96,6 +103,7 @@ struct TuneOpts {
     int fixed_unroll = 0;
     int max_W = 0;  // largest merge piece allowed (0: no limit)
     bool rowblock = true;  // the row-block kernel may be a candidate
+    bool panels = true;    // column panels may be a candidate
     // row statistics already known (longest row, rows of >= 1024 entries):
     // no statistics pass
     bool known_stats = false;

@@ -71,14 +71,18 @@ struct MaxTimes {
 // inside a slot and the butterfly order are fixed.
 
 // One workgroup's rows of the row-split product (rows blk * R .. blk * R + R - 1
-// with R = rows per workgroup) for column tile `coltile`.
+// with R = rows per workgroup) for column tile `coltile`. Row i's entries
+// run from rowbeg[i] to rowend[i] (the whole row: rowptr and rowptr + 1);
+// with `accumulate` the row's sum is added to C instead of written.
 template <class S, int VEC, int U, class R = PlusTimes, bool SHORT = false>
-__device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
+__device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowbeg,
+                                               const int* __restrict__ rowend,
                                                const int* __restrict__ colind,
                                                const typename S::T* __restrict__ vals,
                                                const typename S::T* __restrict__ B,
                                                float* __restrict__ C, int64_t m, int n, int64_t ld,
-                                               int g_log2, int ts_log2, int64_t blk, int coltile) {
+                                               int g_log2, int ts_log2, int64_t blk, int coltile,
+                                               bool accumulate) {
     const int lane = threadIdx.x & (kWave - 1);
     const int tl_log2 = g_log2 + ts_log2;  // lanes per team (log2), <= 6
     const int TL = 1 << tl_log2;
@@ -93,8 +97,8 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
     const int64_t row = (blk << rpb_log2) + (threadIdx.x >> tl_log2);
     int p0 = 0, p1 = 0;
     if (row < m) {
-        p0 = __builtin_nontemporal_load(rowptr + row);
-        p1 = __builtin_nontemporal_load(rowptr + row + 1);
+        p0 = __builtin_nontemporal_load(rowbeg + row);
+        p1 = __builtin_nontemporal_load(rowend + row);
     }
     float acc[VEC];
 #pragma unroll
@@ -201,7 +205,16 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowptr,
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[e] = R::add(acc[e], __shfl_xor(acc[e], off, kWave));
     }
-    if (slot == 0 && row < m && col_ok) store_out<VEC>(C + row * ld + col, acc);
+    if (slot == 0 && row < m && col_ok) {
+        if (accumulate) {
+            // earlier panels' sum first, then this panel's
+            float old[VEC];
+            load_f32<VEC>(C + row * ld + col, old);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] = R::add(old[e], acc[e]);
+        }
+        store_out<VEC>(C + row * ld + col, acc);
+    }
 }
 
 // ---------------------------------------------------------------- merge-based
@@ -483,18 +496,20 @@ __device__ __forceinline__ void merge_fixup_piece(float* __restrict__ C, int64_t
 // ---------------------------------------------------------------- kernels
 
 template <class S, int VEC, int U, class R, bool SHORT>
-__global__ __launch_bounds__(kBlock) void k_rowsplit(const int* __restrict__ rowptr,
+__global__ __launch_bounds__(kBlock) void k_rowsplit(const int* __restrict__ rowbeg,
+                                                      const int* __restrict__ rowend,
                                                       const int* __restrict__ colind,
                                                       const typename S::T* __restrict__ vals,
                                                       const typename S::T* __restrict__ B,
                                                       float* __restrict__ C, int64_t m, int n,
                                                       int64_t ld, int g_log2, int ts_log2,
-                                                      TileOrder ord) {
+                                                      TileOrder ord, int accumulate) {
     const int rpb_log2 = (6 - g_log2 - ts_log2) + 2;
     const int64_t nblk = (m + (int64_t(1) << rpb_log2) - 1) >> rpb_log2;
     for (int64_t t = xcd_remap(blockIdx.x, gridDim.x); t < nblk; t += gridDim.x)
-        rowsplit_block<S, VEC, U, R, SHORT>(rowptr, colind, vals, B, C, m, n, ld, g_log2,
-                                            ts_log2, tile_order(t, ord), blockIdx.y);
+        rowsplit_block<S, VEC, U, R, SHORT>(rowbeg, rowend, colind, vals, B, C, m, n, ld,
+                                            g_log2, ts_log2, tile_order(t, ord), blockIdx.y,
+                                            accumulate != 0);
 }
 
 template <class S, int VEC, int U, class R, bool NZ>
@@ -533,14 +548,15 @@ hipError_t launch_one(bool merge, const Shape& s, const ForwardArgs& a, hipStrea
         const int64_t need = (a.m + rows_per_block - 1) / rows_per_block;
         const uint32_t grid = (uint32_t)(need < (1 << 22) ? need : (1 << 22));
         const TileOrder ord = make_tile_order(s.plane_rows, s.strip_rows, rows_per_block, need);
+        const int* rowend = a.rowend ? a.rowend : a.rowptr + 1;
         if (s.short_addr)
             hipLaunchKernelGGL((k_rowsplit<S, VEC, U, R, true>), dim3(grid, s.col_tiles),
-                               dim3(kBlock), 0, st, a.rowptr, a.colind, vals, B, a.C, a.m,
-                               (int)a.n, a.ld, s.g_log2, s.ts_log2, ord);
+                               dim3(kBlock), 0, st, a.rowptr, rowend, a.colind, vals, B, a.C,
+                               a.m, (int)a.n, a.ld, s.g_log2, s.ts_log2, ord, a.accumulate);
         else
             hipLaunchKernelGGL((k_rowsplit<S, VEC, U, R, false>), dim3(grid, s.col_tiles),
-                               dim3(kBlock), 0, st, a.rowptr, a.colind, vals, B, a.C, a.m,
-                               (int)a.n, a.ld, s.g_log2, s.ts_log2, ord);
+                               dim3(kBlock), 0, st, a.rowptr, rowend, a.colind, vals, B, a.C,
+                               a.m, (int)a.n, a.ld, s.g_log2, s.ts_log2, ord, a.accumulate);
     } else {
         const dim3 grid((uint32_t)a.P, s.col_tiles);
         if (s.nz)

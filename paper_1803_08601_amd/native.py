@@ -33,7 +33,8 @@ class spmm_config(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("vec", ctypes.c_int32),
                 ("lanes_per_row", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("items_per_wg", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
-                ("rows_per_block", ctypes.c_int32), ("tile_order", ctypes.c_int32)]
+                ("rows_per_block", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("col_panels", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -103,7 +103,7 @@ def test_config_struct_layout(tmp_path):
     against include/spmm.h prints every field's offset and each size."""
     import shutil
     import subprocess
-    assert ctypes.sizeof(nv.spmm_config) == 32
+    assert ctypes.sizeof(nv.spmm_config) == 36
     assert ctypes.sizeof(nv.spmm_problem) == 5 * 8 + 5 * 8
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")
@@ -166,18 +166,19 @@ def test_noalloc_degenerate_sizes_are_no_ops():
 def test_tune_cache_file_round_trip(tmp_path):
     """A loaded tune-cache entry is kept and written back unchanged; files that
     are missing, of another format or malformed are refused."""
-    line = "0 100 100 900 8 8 20 0 0 0 0 1  1 4 8 2 2048 0 0 0  0.25"
+    line = "0 100 100 900 8 8 20 0 0 0 0 1 1  1 4 8 2 2048 0 0 0 0  0.25"
     f = tmp_path / "t.txt"
-    f.write_text("spmm-tune-cache 1\n" + line + "\n")
+    f.write_text("spmm-tune-cache 2\n" + line + "\n")
     nv.spmm_tune_cache_load(str(f))
     g = tmp_path / "u.txt"
     nv.spmm_tune_cache_save(str(g))
     rows = g.read_text().splitlines()
-    assert rows[0] == "spmm-tune-cache 1"
+    assert rows[0] == "spmm-tune-cache 2"
     assert [r.split() for r in rows[1:]].count(line.split()) == 1
     bad = tmp_path / "bad.txt"
-    for text in ("spmm-tune-cache 1\n1 2 3\n", "spmm-tune-cache 2\n", "something else\n",
-                 "spmm-tune-cache 1\n" + line.replace(" 1 4 8 2", " 7 4 8 2") + "\n"):
+    for text in ("spmm-tune-cache 2\n1 2 3\n", "spmm-tune-cache 1\n" + line + "\n",
+                 "something else\n",
+                 "spmm-tune-cache 2\n" + line.replace(" 1 4 8 2", " 7 4 8 2") + "\n"):
         bad.write_text(text)
         with pytest.raises(nv.SpmmError) as ei:
             nv.spmm_tune_cache_load(str(bad))

@@ -1,13 +1,12 @@
 """The sparse-versus-dense matrices (Fig. 7: 100k x 100k with a fixed number
 of distinct random columns per row, n = 64) at 1 % and 10 % density, planned
-by timing as the benchmark plans them, and cut into column panels as the
-benchmark's 2-D tiling measurement does: sampled rows of C against the FP64
-oracle on the same inputs."""
+by timing as the benchmark plans them, and with 8 and 16 column panels as
+the benchmark's 2-D tiling measurement runs them: sampled rows of C against
+the FP64 oracle on the same inputs."""
 import numpy as np
 import pytest
 import torch
 
-import bench
 import oracle
 from paper_1803_08601_amd import native as nv
 from paper_1803_08601_amd import workloads as wl
@@ -45,16 +44,14 @@ def test_crossover_matrix_sampled_rows(density):
     plan.execute(vals, Bt, C)
     torch.cuda.synchronize()
     assert rel_err(C[torch.as_tensor(rows, device="cuda")].cpu().numpy(), ref, Nrm) <= TOL_F32
+    print("autotuned shape", plan.info().config.as_dict(), flush=True)
     plan.close()
-    # column panels: the sum of the panels' products is the product
-    P = 8
-    parts = bench.column_panels(rp, ci, vals, N, N, P)
-    assert sum(int(p[1].numel()) for p in parts) == N * L
-    Cp = torch.empty(P, N, n, device="cuda")
-    for q, (prp, pci, pv, lo, hi) in enumerate(parts):
-        pl = nv.Plan(prp, pci, N, hi - lo, n, nnz=int(pci.numel()), mode="autotune")
-        pl.execute(pv, Bt[lo:hi], Cp[q])
+    # column panels as the benchmark times them (8 and 16 panels)
+    for P in (8, 16):
+        pl = nv.Plan(rp, ci, N, N, n, nnz=N * L,
+                     config=dict(kernel=nv.SPMM_KERNEL_ROWSPLIT, col_panels=P, lanes_per_row=64))
+        C.fill_(float("nan"))
+        pl.execute(vals, Bt, C)
+        torch.cuda.synchronize()
+        assert rel_err(C[torch.as_tensor(rows, device="cuda")].cpu().numpy(), ref, Nrm) <= TOL_F32
         pl.close()
-    C2 = Cp.sum(0)
-    torch.cuda.synchronize()
-    assert rel_err(C2[torch.as_tensor(rows, device="cuda")].cpu().numpy(), ref, Nrm) <= TOL_F32

@@ -23,7 +23,8 @@ CFGS = [dict(kernel=nv.SPMM_KERNEL_ROWSPLIT, lanes_per_row=0, unroll=4),
         dict(kernel=nv.SPMM_KERNEL_MERGE, items_per_wg=64, unroll=1),
         dict(kernel=nv.SPMM_KERNEL_MERGE, items_per_wg=1024, unroll=8),
         dict(kernel=nv.SPMM_KERNEL_NZSPLIT, items_per_wg=64, unroll=2),
-        dict(kernel=nv.SPMM_KERNEL_ROWBLOCK, rows_per_block=4, unroll=4)]
+        dict(kernel=nv.SPMM_KERNEL_ROWBLOCK, rows_per_block=4, unroll=4),
+        dict(kernel=nv.SPMM_KERNEL_ROWSPLIT, lanes_per_row=32, unroll=4, col_panels=3)]
 
 MATS = {
     "power_law": lambda: wl.power_law(seed=41, m=20_000, cap=20_000, values="uniform"),
@@ -45,7 +46,7 @@ def run(A, vals, B, n, sr, cfg):
 
 @pytest.mark.parametrize("name", sorted(MATS))
 @pytest.mark.parametrize("sr", sorted(SEMIRINGS))
-@pytest.mark.parametrize("cfg", CFGS, ids=["rs", "rs64", "mg64", "mg1024", "nz64", "rb4"])
+@pytest.mark.parametrize("cfg", CFGS, ids=["rs", "rs64", "mg64", "mg1024", "nz64", "rb4", "cp3"])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_semiring_exact(name, sr, cfg, dtype):
     A = MATS[name]()

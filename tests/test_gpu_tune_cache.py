@@ -28,11 +28,13 @@ def test_loaded_shape_is_used(tmp_path):
     assert len(key) == 1
     parts = key[0].split()
     forced = {"kernel": nv.SPMM_KERNEL_ROWSPLIT, "vec": 4, "lanes_per_row": 64, "unroll": 1,
-              "items_per_wg": 1024, "tile_cols": 0, "rows_per_block": 0, "tile_order": 0}
+              "items_per_wg": 1024, "tile_cols": 0, "rows_per_block": 0, "tile_order": 0,
+              "col_panels": 0}
     assert forced != tuned
-    parts[12:20] = [str(forced[k]) for k in ("kernel", "vec", "lanes_per_row", "unroll",
+    # 13 key fields, then the 9 config fields
+    parts[13:22] = [str(forced[k]) for k in ("kernel", "vec", "lanes_per_row", "unroll",
                                              "items_per_wg", "tile_cols", "rows_per_block",
-                                             "tile_order")]
+                                             "tile_order", "col_panels")]
     f.write_text(rows[0] + "\n" + " ".join(parts) + "\n")
     nv.spmm_tune_cache_load(str(f))
     plan = nv.Plan(rp, ci, A.m, A.k, n, nnz=A.nnz, mode="autotune")
