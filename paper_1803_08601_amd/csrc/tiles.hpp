@@ -4,6 +4,8 @@
 
 #include <limits.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -164,13 +166,26 @@ __device__ __forceinline__ void rowsplit_block(const int* __restrict__ rowbeg,
                 }
                 if (col_ok && k + U <= lim) {
                     // a whole block of this slot's entries: no per-entry checks
-                    float b[U][VEC];
+                    if constexpr (std::is_same<S, BF16>::value && VEC == 8 &&
+                                  std::is_same<R, PlusTimes>::value && U % 2 == 0) {
+                        // BF16: two entries at a time by paired dot products
+                        u32x4 raw[U];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) load_row<S, VEC>(b_row(c[u]), b[u]);
+                        for (int u = 0; u < U; ++u)
+                            raw[u] = *reinterpret_cast<const u32x4*>(b_row(c[u]));
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
+                        for (int u = 0; u < U; u += 2)
+                            dot2_pair_bf16(raw[u], raw[u + 1], bf16_pair_bits(v[u], v[u + 1]),
+                                           acc);
+                    } else {
+                        float b[U][VEC];
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
+                        for (int u = 0; u < U; ++u) load_row<S, VEC>(b_row(c[u]), b[u]);
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
+                        }
                     }
                 } else {
                     bool ok[U];
@@ -363,32 +378,70 @@ __device__ __forceinline__ void merge_tile(const int* __restrict__ rowptr,
         rend = r < nr ? rowend(r) : INT_MAX;
     };
 
+    constexpr bool kPairs = std::is_same<S, BF16>::value && VEC == 8 &&
+                            std::is_same<R, PlusTimes>::value && U % 2 == 0;
     for (int jb = js; jb < je; jb += U) {
         int c[U];
         float v[U];
-        float b[U][VEC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool ok = jb + u < je;
             c[u] = ok ? s_col[jb + u] : 0;
             v[u] = ok ? s_val[jb + u] : 0.f;
         }
+        if constexpr (kPairs) {
+            // BF16: raw 16-byte chunks; two entries of one row at a time by
+            // paired dot products, an entry alone where a row ends between
+            u32x4 raw[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (jb + u < je && col_ok) {
-                load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
-            } else {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
+            for (int u = 0; u < U; ++u) {
+                if (jb + u < je && col_ok)
+                    raw[u] = *reinterpret_cast<const u32x4*>(B + (int64_t)c[u] * ld + col);
+                else
+                    raw[u] = u32x4{0u, 0u, 0u, 0u};
             }
-        }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = jb + u;
-            if (j < je) {
-                while (rend <= j) emit();
+            for (int u = 0; u < U; u += 2) {
+                const int j = jb + u;
+                if (j < je) {
+                    while (rend <= j) emit();
+                    if (j + 1 < je && rend > j + 1) {
+                        dot2_pair_bf16(raw[u], raw[u + 1], bf16_pair_bits(v[u], v[u + 1]), acc);
+                    } else {
+                        float b[VEC];
+                        unpack2(raw[u].x, b + 0, BF16{}); unpack2(raw[u].y, b + 2, BF16{});
+                        unpack2(raw[u].z, b + 4, BF16{}); unpack2(raw[u].w, b + 6, BF16{});
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
+                        for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v[u], b[e], acc[e]);
+                        if (j + 1 < je) {
+                            while (rend <= j + 1) emit();
+                            unpack2(raw[u + 1].x, b + 0, BF16{}); unpack2(raw[u + 1].y, b + 2, BF16{});
+                            unpack2(raw[u + 1].z, b + 4, BF16{}); unpack2(raw[u + 1].w, b + 6, BF16{});
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e) acc[e] = fmaf(v[u + 1], b[e], acc[e]);
+                        }
+                    }
+                }
+            }
+        } else {
+            float b[U][VEC];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (jb + u < je && col_ok) {
+                    load_row<S, VEC>(B + (int64_t)c[u] * ld + col, b[u]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) b[u][e] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = jb + u;
+                if (j < je) {
+                    while (rend <= j) emit();
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[e] = R::mac(acc[e], v[u], b[u][e]);
+                }
             }
         }
     }
