@@ -523,3 +523,33 @@ def test_rule_mode_choice():
         if want == RB:
             assert info.config.rows_per_block == 2
         check(A, dev(A.vals), dev(B), n, C)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_rowsplit_infinite_b_row_reaches_only_its_rows(dtype):
+    """Row split never lets a step past a row's last entry touch the sum: with
+    B row 0 infinite, only the rows that hold column 0 are infinite, and every
+    other row matches the oracle - for every team width and unroll (rows of
+    8 to 27 entries leave partial blocks of U steps) and with column panels."""
+    A = wl.stencil27(g=12)
+    n = 16
+    B = wl.dense(46, A.k, n)
+    B[0, :] = np.inf
+    rows = np.repeat(np.arange(A.m), A.row_lengths())
+    holds = np.zeros(A.m, bool)
+    holds[rows[A.colind == 0]] = True
+    Bf = B.copy()
+    Bf[0, :] = 0.0
+    vt, Bt, Bft = dev(A.vals, DT[dtype]), dev(B, DT[dtype]), dev(Bf, DT[dtype])
+    Cref, N = oracle_product(A.rowptr, A.colind, vt, Bft, n)
+    tol = TOL_F32
+    for lpr in (4, 16, 64):
+        for u in (2, 4, 8):
+            for P in (0, 3):
+                cfg = dict(kernel=nv.SPMM_KERNEL_ROWSPLIT, lanes_per_row=lpr, unroll=u,
+                           col_panels=P)
+                C, plan = run(A, vt, Bt, n, config=cfg)
+                c = C.cpu().numpy()
+                assert holds.sum() == 8 and np.all(np.isinf(c[holds]))
+                assert np.all(np.isfinite(c[~holds]))
+                assert rel_err(c[~holds], Cref[~holds], N[~holds]) <= tol, (lpr, u, P)
