@@ -37,6 +37,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
+# the autotuner's choices from the traced runs the counter records were taken
+# on (one line per matrix key); loaded by default so that every row plans the
+# shapes its counters describe
+BENCH_TUNE_CACHE = os.path.join(ROOT, "profiles", "bench_tune_cache.txt")
 TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, scaled by a 1 GiB copy: "
                   "bytes between the L2 caches and the fabric, which include Infinity Cache "
                   "(MALL) hits - an upper bound on DRAM traffic, not DRAM traffic itself")
@@ -959,7 +963,9 @@ def copy_scale(d, name, bytes_per_copy):
 def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
     """Turn the rocprofv3 runs under run_dir into counter records
     (profiles/hbm_counters.json) and one summary per workload family.
-    Layout: run_dir/copy/{fetch,write}: `bench.py --copy-calibration` under
+    Layout: run_dir/tune.txt: the autotuner's choices every pass loads and
+    extends (seeded with profiles/bench_tune_cache.txt);
+    run_dir/copy/{fetch,write}: `bench.py --copy-calibration` under
     `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE`; run_dir/<row>/: manifest.json
     and cmd.txt (the bench arguments) written by the profiled run,
     fetch/, write/, l2/ (--pmc TCC_HIT_sum TCC_MISS_sum TA_TA_BUSY_sum
@@ -1023,12 +1029,30 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
                    "ta_busy": None if ta is None else round(ta, 3),
                    "bytes_min": m["bytes_min"], "bytes_gather": m["bytes_gather"],
                    "kernel_ms_cold_mean": m["kernel_ms_cold_mean"], "profile": fam[0]}
-            lst = [r for r in records.get(m["row"], []) if r.get("config") != m["config"]]
+            # records taken on other kernel sources describe other kernels: dropped
+            lst = [r for r in records.get(m["row"], [])
+                   if r.get("config") != m["config"] and r.get("kernel_source_sha") == sha]
             records[m["row"]] = [rec] + lst
             rows.append((fam, m, rec, per, (args, l2_names), stats))
     with open(path, "w") as fh:
         json.dump(records, fh, indent=1, sort_keys=True)
         fh.write("\n")
+    # the traced runs' autotuner choices, one line per matrix key (the bench
+    # loads them, so its rows plan the shapes recorded here)
+    lines, header = {}, None
+    for tf in sorted(glob.glob(os.path.join(run_dir, "*", "tune.txt")) +
+                     glob.glob(os.path.join(run_dir, "tune.txt"))):
+        rows_ = open(tf).read().splitlines()
+        if not rows_:
+            continue
+        header = rows_[0]
+        for ln in rows_[1:]:
+            f_ = ln.split()
+            if f_:
+                lines[tuple(f_[:13])] = ln
+    if header is not None:
+        with open(os.path.join(profiles, "bench_tune_cache.txt"), "w") as fh:
+            fh.write(header + "\n" + "\n".join(lines[k_] for k_ in sorted(lines)) + "\n")
     rp = "rocprofv3"
     for fam in ROW_FAMILIES:
         mine = [r for r in rows if r[0] is fam]
@@ -1040,9 +1064,10 @@ def record_counters(run_dir, profiles=os.path.join(ROOT, "profiles")):
              "cold-cache steps), scaled by the same counters on a plain 1 GiB copy; it is measured "
              "between the L2 caches and the fabric, so it includes Infinity Cache hits. Bytes_min: "
              "A, B and C moved once; gather model: every entry fetching its B row.", "",
-             "Commands (repository root):", "", "```"]
+             "Commands (repository root):", "", "```",
+             "cp profiles/bench_tune_cache.txt <run>/tune.txt"]
         for a_, l2n in sorted({r[4] for r in mine}):
-            tc = "--tune-cache <run>/<row>/tune.txt"
+            tc = "--tune-cache <run>/tune.txt"
             L += [f"{rp} --kernel-trace --stats --output-format csv -d <run>/<row>/trace -o r -- "
                   f"python3 bench.py {a_} {tc} --manifest <run>/<row>/manifest.json",
                   f"{rp} --pmc FETCH_SIZE --output-format csv -d <run>/<row>/fetch -o r -- "
@@ -1148,6 +1173,9 @@ def main():
                     help="sparse versus dense product over density (100k x 100k, n = 64)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--retune", action="store_true",
+                    help="time the autotuner's candidates afresh instead of loading the "
+                         "choices kept in profiles/bench_tune_cache.txt")
     ap.add_argument("--summary", default=None, metavar="FILE",
                     help="with a sweep mode: also write its records as a markdown table")
     ap.add_argument("--tune-cache", default=None, metavar="FILE",
@@ -1172,6 +1200,8 @@ def main():
         if os.path.exists(args.tune_cache):
             nv.spmm_tune_cache_load(args.tune_cache)
         atexit.register(nv.spmm_tune_cache_save, args.tune_cache)
+    elif not args.retune and os.path.exists(BENCH_TUNE_CACHE):
+        nv.spmm_tune_cache_load(BENCH_TUNE_CACHE)
     manifest = [] if args.manifest else None
 
     def write_manifest():

@@ -94,9 +94,14 @@ def test_record_counters_from_profiler_output(tmp_path):
         "patterns": [r"\bk_merge<", r"\bk_merge_fixup<"], "bytes_min": 100_000,
         "bytes_gather": 400_000, "kernel_ms_cold_mean": 0.5}]))
     (rowd / "cmd.txt").write_text("--quick --no-cpu-baseline --steps 2 --warmup 1")
+    key = "0 1 2 3 4 5 6 7 8 9 10 1 1"
+    (rowd / "tune.txt").write_text(f"spmm-tune-cache 2\n{key}  2 4 16 2 2048 0 0 0 0  0.5\n")
     prof = tmp_path / "profiles"
     prof.mkdir()
     recs = bench.record_counters(str(run), profiles=str(prof))
+    # the traced run's autotuner choices are kept for the bench to load
+    assert (prof / "bench_tune_cache.txt").read_text().splitlines() == [
+        "spmm-tune-cache 2", f"{key}  2 4 16 2 2048 0 0 0 0  0.5"]
     r = recs["powerlaw-n64-f32"][0]
     assert r["fetch_scale"] == 2.0 and r["write_scale"] == 1.0
     assert r["fetch_kib"] == 25.0 + 2.5 and r["write_kib"] == 7.0 + 2.0
