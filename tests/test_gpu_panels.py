@@ -138,3 +138,23 @@ def test_panels_backward_and_autotune():
     assert rel_err(C.cpu().numpy(), ref, N) <= TOL_F32
     print("autotuned shape", tuned.info().config.as_dict(), flush=True)
     tuned.close()
+
+
+def test_panels_with_column_tiles_strips_and_more_panels_than_columns():
+    """Panels combined with column tiles (grid y), with the strip order of a
+    stencil, and with more panels than A has columns (empty panels): all
+    integer-exact against the oracle."""
+    rng = np.random.default_rng(11)
+    cases = [
+        (MATS["wide"](), 64, dict(col_panels=4, tile_cols=32, lanes_per_row=64, unroll=4)),
+        (wl.stencil27(g=40), 32, dict(col_panels=2, tile_order=2, lanes_per_row=16, unroll=4)),
+        (wl.random_csr(12, 500, 3, density=0.6), 16, dict(col_panels=8, unroll=2)),
+    ]
+    for A, n, extra in cases:
+        vals = rng.integers(-8, 9, A.nnz).astype(np.float32)
+        B = rng.integers(-8, 9, (A.k, n)).astype(np.float32)
+        cfg = dict(kernel=nv.SPMM_KERNEL_ROWSPLIT, **extra)
+        got, info = run(A, dev(vals), dev(B), n, cfg)
+        assert info.config.col_panels == extra["col_panels"]
+        ref = oracle.spmm(A.rowptr, A.colind, vals, B)
+        assert np.array_equal(got.astype(np.float64), ref), extra
