@@ -778,6 +778,43 @@ def table_size_sweep(n=64):
     return recs
 
 
+def gather_ceiling():
+    """The device's rate for the products' access to B alone: lanes read
+    rows of 64, 256 and 512 bytes (n = 16, 64 and 128 in float32, 16 bytes a
+    lane, eight rows in flight per lane group) at pseudo-random indices of a
+    table of 16 KB (one CU's L1), 2 MB (within an XCD's 4 MB L2), 64 MB and
+    256 MB (within and at the size of the 256 MB MALL), with no reads of A and
+    no writes of C (the library's gather calibration kernel, 524,288 lanes,
+    512 rows each, mean of 5 launches timed with events)."""
+    import torch
+    from paper_1803_08601_amd import native as nv
+    threads, steps = 2048 * 256, 512
+    table = torch.rand(64 << 20, device="cuda")  # 256 MB
+    out = torch.empty(threads, device="cuda")
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    recs = []
+    for row_bytes in (64, 256, 512):
+        for table_bytes in (16 << 10, 2 << 20, 64 << 20, 256 << 20):
+            rows = table_bytes // row_bytes
+            for _ in range(2):
+                nv.spmm_calibrate_gather(table, rows, row_bytes, steps, out, threads, st.cuda_stream)
+            e0.record(st)
+            for _ in range(5):
+                nv.spmm_calibrate_gather(table, rows, row_bytes, steps, out, threads, st.cuda_stream)
+            e1.record(st)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            nbytes = threads * steps * 16
+            rec = {"row_bytes": row_bytes, "table_MB": round(table_bytes / 2**20, 3),
+                   "ms": round(ms, 4), "TBs": round(nbytes / (ms * 1e-3) / 1e12, 2),
+                   "G_rows_per_s": round(nbytes / row_bytes / (ms * 1e-3) / 1e9, 1),
+                   "B_per_clk_per_CU": round(nbytes / (ms * 1e-3) / (256 * 2.4e9), 1)}
+            print(json.dumps(rec), flush=True)
+            recs.append(rec)
+    return recs
+
+
 def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1), panels=(4, 8, 16)):
     """Sparse versus dense (Fig. 7): a 100k x 100k matrix with a fixed share
     of distinct random columns in every row times a 100k x 64 B, SpMM (plan by
@@ -1169,6 +1206,8 @@ def main():
                          "runs of empty rows")
     ap.add_argument("--table-size-sweep", action="store_true",
                     help="the same entries against B tables from 256 MB down to 4 MB")
+    ap.add_argument("--gather-ceiling", action="store_true",
+                    help="the device's rate for random row gathers alone, by row and table size")
     ap.add_argument("--crossover", action="store_true",
                     help="sparse versus dense product over density (100k x 100k, n = 64)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -1240,6 +1279,10 @@ def main():
     if args.rowblock_sweep:
         summarise(rowblock_sweep(), "Row blocks against row split and merge path",
                   rowblock_sweep.__doc__.strip().replace("\n    ", " "))
+        return
+    if args.gather_ceiling:
+        summarise(gather_ceiling(), "Random row gathers alone: the ceiling of the B access",
+                  gather_ceiling.__doc__.strip().replace("\n    ", " "))
         return
     if args.table_size_sweep:
         summarise(table_size_sweep(args.n), "Gather rate against the size of B",

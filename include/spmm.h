@@ -427,6 +427,20 @@ int spmm_batch_destroy(spmm_batch_t batch);
 int spmm_csr_validate(const int32_t* A_rowptr, const int32_t* A_colind, int64_t m, int64_t k,
                       int64_t nnz, void* stream);
 
+/* Measurement aid for the roofline of the gather kernels (no product uses
+ * it): `threads` lanes (a multiple of 256) read rows of `row_bytes` bytes
+ * (64, 256 or 512; 16 bytes per lane, row_bytes / 16 lanes per row) at
+ * pseudo-random row indices of `table` (device, 16-byte aligned, table_rows
+ * rows of row_bytes bytes, table_rows a power of two up to 2^31), `steps`
+ * rows per lane group
+ * (a multiple of 8, eight in flight), and write one float per lane to `out`
+ * (device, `threads` floats) - the access the products make to B, without
+ * their reads of A and writes of C. Bytes read: threads * steps * 16.
+ * Enqueue only: time it with events on `stream`. SPMM_ERR_INVALID on a bad
+ * argument. */
+int spmm_calibrate_gather(const void* table, int64_t table_rows, int32_t row_bytes,
+                          int32_t steps, float* out, int64_t threads, void* stream);
+
 const char* spmm_status_string(int status);
 const char* spmm_last_error(void);
 /* Library version, e.g. "0.1.0". */

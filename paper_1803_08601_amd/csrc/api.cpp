@@ -1349,4 +1349,26 @@ int spmm_csr_validate(const int32_t* A_rowptr, const int32_t* A_colind, int64_t 
     return SPMM_OK;
 }
 
+int spmm_calibrate_gather(const void* table, int64_t table_rows, int32_t row_bytes,
+                          int32_t steps, float* out, int64_t threads, void* stream) {
+    if (!table || !out) return fail(SPMM_ERR_INVALID, "table or out is NULL");
+    if (row_bytes != 64 && row_bytes != 256 && row_bytes != 512)
+        return fail(SPMM_ERR_INVALID, "row_bytes %d: use 64, 256 or 512", row_bytes);
+    if (table_rows < 1 || table_rows > (int64_t(1) << 31) || (table_rows & (table_rows - 1)))
+        return fail(SPMM_ERR_INVALID, "table_rows %lld: a power of two up to 2^31",
+                    (long long)table_rows);
+    if (steps < 8 || steps % 8)
+        return fail(SPMM_ERR_INVALID, "steps %d: a positive multiple of 8", steps);
+    if (threads < spmmk::kBlock || threads % spmmk::kBlock ||
+        threads / spmmk::kBlock > (int64_t(1) << 31) - 1 || threads > (int64_t(1) << 32))
+        return fail(SPMM_ERR_INVALID, "threads %lld: a multiple of %d", (long long)threads,
+                    spmmk::kBlock);
+    if ((reinterpret_cast<uintptr_t>(table) & 15u) != 0)
+        return fail(SPMM_ERR_INVALID, "table is not 16-byte aligned");
+    const hipError_t e = spmmk::launch_calib_gather(table, table_rows, row_bytes, steps, out,
+                                                    threads, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "gather calibration launch");
+    return SPMM_OK;
+}
+
 }  // extern "C"

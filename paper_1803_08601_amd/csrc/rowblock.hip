@@ -229,36 +229,71 @@ __global__ __launch_bounds__(kBlock) void k_rowblock(const int* __restrict__ row
                 const int nvalid = (cnt - slot + TS - 1) >> ts_log2;  // this slot's entries
                 const int* sw = s_w + ebase + (slot << (g_log2 + 1));
                 const float* sv = s_v + (ebase + (slot << (g_log2 + 1))) * RB;
-                for (int k = 0; k < nvalid; k += U) {
+                // Whole steps of U entries, two in flight: the gathers of step
+                // k + U are issued before the adds of step k wait for theirs
+                // (the adds keep the entry order).
+                auto gather = [&](int k0, uint32_t (&w)[U], float (&bv)[U][VEC]) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        w[u] = (uint32_t)sw[k0 + u];
+                        load_row<S, VEC>(b_row(w[u] & kColMask), bv[u]);
+                    }
+                };
+                auto add = [&](int k0, const uint32_t (&w)[U], const float (&bv)[U][VEC]) {
+                    float v[U][RB];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) read_vals<RB>(sv + (k0 + u) * RB, v[u]);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+#pragma unroll
+                        for (int r = 0; r < RB; ++r) {
+                            if (!MASKED || ((w[u] >> (kRowBlockColBits + r)) & 1u)) {
+#pragma unroll
+                                for (int e2 = 0; e2 < VEC; ++e2)
+                                    acc[r][e2] = fmaf(v[u][r], bv[u][e2], acc[r][e2]);
+                            }
+                        }
+                    }
+                };
+                int k = 0;
+                if (col_ok && nvalid >= U) {
+                    uint32_t wA[U], wB[U];
+                    float bA[U][VEC], bB[U][VEC];
+                    gather(0, wA, bA);
+                    for (;;) {
+                        const bool nb = k + 2 * U <= nvalid;
+                        if (nb) gather(k + U, wB, bB);
+                        add(k, wA, bA);
+                        k += U;
+                        if (!nb) break;
+                        const bool na = k + 2 * U <= nvalid;
+                        if (na) gather(k + U, wA, bA);
+                        add(k, wB, bB);
+                        k += U;
+                        if (!na) break;
+                    }
+                }
+                // the last, partial step (every step when this lane's columns
+                // lie past n)
+                for (; k < nvalid; k += U) {
                     uint32_t w[U];
                     float v[U][RB];
                     float bv[U][VEC];
-                    if (col_ok && k + U <= nvalid) {
-                        // a whole step of this slot's entries: no per-entry checks
 #pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            w[u] = (uint32_t)sw[k + u];
-                            load_row<S, VEC>(b_row(w[u] & kColMask), bv[u]);
+                    for (int u = 0; u < U; ++u) {
+                        const bool ok = k + u < nvalid;
+                        w[u] = ok ? (uint32_t)sw[k + u] : 0u;
+                        if (ok) {
+                            read_vals<RB>(sv + (k + u) * RB, v[u]);
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < RB; ++r) v[u][r] = 0.f;
                         }
+                        if (ok && col_ok) {
+                            load_row<S, VEC>(b_row(w[u] & kColMask), bv[u]);
+                        } else {
 #pragma unroll
-                        for (int u = 0; u < U; ++u) read_vals<RB>(sv + (k + u) * RB, v[u]);
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const bool ok = k + u < nvalid;
-                            w[u] = ok ? (uint32_t)sw[k + u] : 0u;
-                            if (ok) {
-                                read_vals<RB>(sv + (k + u) * RB, v[u]);
-                            } else {
-#pragma unroll
-                                for (int r = 0; r < RB; ++r) v[u][r] = 0.f;
-                            }
-                            if (ok && col_ok) {
-                                load_row<S, VEC>(b_row(w[u] & kColMask), bv[u]);
-                            } else {
-#pragma unroll
-                                for (int e2 = 0; e2 < VEC; ++e2) bv[u][e2] = 0.f;
-                            }
+                            for (int e2 = 0; e2 < VEC; ++e2) bv[u][e2] = 0.f;
                         }
                     }
 #pragma unroll

@@ -93,6 +93,7 @@ _SIGS = {
     "spmm_batch_problem_config": [_VP, _I64, _VP],
     "spmm_batch_destroy": [_VP],
     "spmm_csr_validate": [_VP, _VP, _I64, _I64, _I64, _VP],
+    "spmm_calibrate_gather": [_VP, _I64, _I32, _I32, _VP, _I64, _VP],
     "spmm_status_string": [ctypes.c_int],
     "spmm_last_error": [],
     "spmm_version": [],
@@ -293,6 +294,12 @@ def spmm_batch_destroy(batch):
 def spmm_csr_validate(A_rowptr, A_colind, m, k, nnz, stream=None):
     return _check("spmm_csr_validate", lib().spmm_csr_validate(_ptr(A_rowptr), _ptr(A_colind), m,
                                                                k, nnz, _stream(stream)))
+
+
+def spmm_calibrate_gather(table, table_rows, row_bytes, steps, out, threads, stream=None):
+    return _check("spmm_calibrate_gather",
+                  lib().spmm_calibrate_gather(_ptr(table), table_rows, row_bytes, steps, _ptr(out),
+                                              threads, _stream(stream)))
 
 
 # ---------------------------------------------------------------- plan wrapper

@@ -185,3 +185,17 @@ def test_tune_cache_file_round_trip(tmp_path):
         assert ei.value.status == nv.SPMM_ERR_INVALID
     with pytest.raises(nv.SpmmError):
         nv.spmm_tune_cache_load(str(tmp_path / "missing.txt"))
+
+
+@pytest.mark.parametrize("kw", [dict(table=None), dict(out=None), dict(row_bytes=128),
+                                dict(table_rows=0), dict(table_rows=3), dict(table_rows=2**32),
+                                dict(steps=0), dict(steps=12), dict(threads=100),
+                                dict(threads=0), dict(table=ctypes.c_void_p(8 + 4))])
+def test_calibrate_gather_rejects(kw):
+    """The gather calibration refuses bad arguments before any launch."""
+    a = dict(table=ctypes.c_void_p(256), table_rows=1024, row_bytes=256, steps=64,
+             out=ctypes.c_void_p(256), threads=2048)
+    a.update(kw)
+    assert nv.lib().spmm_calibrate_gather(a["table"], a["table_rows"], a["row_bytes"], a["steps"],
+                                          a["out"], a["threads"], None) == nv.SPMM_ERR_INVALID
+    assert nv.spmm_last_error()
