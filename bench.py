@@ -46,12 +46,19 @@ TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, scaled by a
                   "(MALL) hits - an upper bound on DRAM traffic, not DRAM traffic itself")
 
 
+# device sources no product launches (the gather calibration kernel)
+NOT_PRODUCT_SOURCES = {"calib.hip"}
+
+
 def kernel_source_hash():
-    """Hash of the device sources (every .hip and .hpp file of the library):
-    counters taken on another version of them do not describe the kernels."""
+    """Hash of the device sources of the products (every .hip and .hpp file of
+    the library but the calibration kernel): counters taken on another version
+    of them do not describe the kernels."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1803_08601_amd", "csrc")
     for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        if os.path.basename(f) in NOT_PRODUCT_SOURCES:
+            continue
         h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
@@ -780,8 +787,9 @@ def table_size_sweep(n=64):
 
 def gather_ceiling():
     """The device's rate for the products' access to B alone: lanes read
-    rows of 64, 256 and 512 bytes (n = 16, 64 and 128 in float32, 16 bytes a
-    lane, eight rows in flight per lane group) at pseudo-random indices of a
+    rows of 32, 64, 128, 256 and 512 bytes (n = 8, 16, 32, 64 and 128 in
+    float32; 128 bytes is also n = 64 in bfloat16; 16 bytes a lane, eight
+    rows in flight per lane group) at pseudo-random indices of a
     table of 16 KB (one CU's L1), 2 MB (within an XCD's 4 MB L2), 64 MB and
     256 MB (within and at the size of the 256 MB MALL), with no reads of A and
     no writes of C (the library's gather calibration kernel, 524,288 lanes,
@@ -794,7 +802,7 @@ def gather_ceiling():
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     recs = []
-    for row_bytes in (64, 256, 512):
+    for row_bytes in (32, 64, 128, 256, 512):
         for table_bytes in (16 << 10, 2 << 20, 64 << 20, 256 << 20):
             rows = table_bytes // row_bytes
             for _ in range(2):

@@ -429,7 +429,7 @@ int spmm_csr_validate(const int32_t* A_rowptr, const int32_t* A_colind, int64_t 
 
 /* Measurement aid for the roofline of the gather kernels (no product uses
  * it): `threads` lanes (a multiple of 256) read rows of `row_bytes` bytes
- * (64, 256 or 512; 16 bytes per lane, row_bytes / 16 lanes per row) at
+ * (32, 64, 128, 256 or 512; 16 bytes per lane, row_bytes / 16 lanes per row) at
  * pseudo-random row indices of `table` (device, 16-byte aligned, table_rows
  * rows of row_bytes bytes, table_rows a power of two up to 2^31), `steps`
  * rows per lane group

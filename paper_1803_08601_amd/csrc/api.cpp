@@ -1352,8 +1352,9 @@ int spmm_csr_validate(const int32_t* A_rowptr, const int32_t* A_colind, int64_t 
 int spmm_calibrate_gather(const void* table, int64_t table_rows, int32_t row_bytes,
                           int32_t steps, float* out, int64_t threads, void* stream) {
     if (!table || !out) return fail(SPMM_ERR_INVALID, "table or out is NULL");
-    if (row_bytes != 64 && row_bytes != 256 && row_bytes != 512)
-        return fail(SPMM_ERR_INVALID, "row_bytes %d: use 64, 256 or 512", row_bytes);
+    if (row_bytes != 32 && row_bytes != 64 && row_bytes != 128 && row_bytes != 256 &&
+        row_bytes != 512)
+        return fail(SPMM_ERR_INVALID, "row_bytes %d: use 32, 64, 128, 256 or 512", row_bytes);
     if (table_rows < 1 || table_rows > (int64_t(1) << 31) || (table_rows & (table_rows - 1)))
         return fail(SPMM_ERR_INVALID, "table_rows %lld: a power of two up to 2^31",
                     (long long)table_rows);

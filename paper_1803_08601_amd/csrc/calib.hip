@@ -46,7 +46,9 @@ hipError_t launch_calib_gather(const void* table, int64_t rows, int row_bytes, i
     const dim3 grid((uint32_t)(threads / kBlock));
     const f32x4* T = static_cast<const f32x4*>(table);
     switch (row_bytes) {
+    case 32: hipLaunchKernelGGL(k_calib_gather<2>, grid, dim3(kBlock), 0, st, T, mask, steps, out); break;
     case 64: hipLaunchKernelGGL(k_calib_gather<4>, grid, dim3(kBlock), 0, st, T, mask, steps, out); break;
+    case 128: hipLaunchKernelGGL(k_calib_gather<8>, grid, dim3(kBlock), 0, st, T, mask, steps, out); break;
     case 256: hipLaunchKernelGGL(k_calib_gather<16>, grid, dim3(kBlock), 0, st, T, mask, steps, out); break;
     case 512: hipLaunchKernelGGL(k_calib_gather<32>, grid, dim3(kBlock), 0, st, T, mask, steps, out); break;
     default: return hipErrorInvalidValue;

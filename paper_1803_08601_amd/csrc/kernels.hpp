@@ -118,7 +118,7 @@ hipError_t launch_sddmm(int dtype, int vec, int unroll, int g_log2, int col_tile
                         hipStream_t st);
 
 // Gather calibration: threads (a multiple of kBlock) lanes read rows of
-// row_bytes (64, 256 or 512) at pseudo-random indices of a table of rows
+// row_bytes (32, 64, 128, 256 or 512) at pseudo-random indices of a table of rows
 // rows (a power of two), steps reads each (a multiple of 8); one float per
 // thread into out.
 hipError_t launch_calib_gather(const void* table, int64_t rows, int row_bytes, int steps,

@@ -187,7 +187,7 @@ def test_tune_cache_file_round_trip(tmp_path):
         nv.spmm_tune_cache_load(str(tmp_path / "missing.txt"))
 
 
-@pytest.mark.parametrize("kw", [dict(table=None), dict(out=None), dict(row_bytes=128),
+@pytest.mark.parametrize("kw", [dict(table=None), dict(out=None), dict(row_bytes=96), dict(row_bytes=1024),
                                 dict(table_rows=0), dict(table_rows=3), dict(table_rows=2**32),
                                 dict(steps=0), dict(steps=12), dict(threads=100),
                                 dict(threads=0), dict(table=ctypes.c_void_p(8 + 4))])

@@ -20,7 +20,7 @@ def _mix(x):
     return x
 
 
-@pytest.mark.parametrize("row_bytes", [64, 256, 512])
+@pytest.mark.parametrize("row_bytes", [32, 64, 128, 256, 512])
 def test_calibrate_gather_reads_the_indexed_rows(row_bytes):
     rows, steps, threads = 64, 16, 512
     G = row_bytes // 16
