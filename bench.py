@@ -823,6 +823,35 @@ def gather_ceiling():
     return recs
 
 
+def live_gather_ceiling(row_bytes, table_bytes):
+    """The gather calibration kernel's rate (rows/s) for rows of row_bytes
+    from a table of about table_bytes (the power of two of rows nearest in
+    log scale), or None for a row size it does not take."""
+    import math
+    import torch
+    from paper_1803_08601_amd import native as nv
+    if row_bytes not in (32, 64, 128, 256, 512):
+        return None
+    rows = 1 << max(0, round(math.log2(max(1, table_bytes // row_bytes))))
+    threads, steps = 2048 * 256, 512
+    table = torch.rand(rows * row_bytes // 4, device="cuda")
+    out = torch.empty(threads, device="cuda")
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        nv.spmm_calibrate_gather(table, rows, row_bytes, steps, out, threads, st.cuda_stream)
+    e0.record(st)
+    for _ in range(5):
+        nv.spmm_calibrate_gather(table, rows, row_bytes, steps, out, threads, st.cuda_stream)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del table, out
+    torch.cuda.empty_cache()
+    return {"rows_per_s": threads * steps * 16 / row_bytes / (ms * 1e-3), "row_bytes": row_bytes,
+            "table_bytes": rows * row_bytes}
+
+
 def crossover(n=64, densities=(0.001, 0.0025, 0.005, 0.01, 0.02, 0.05, 0.1), panels=(4, 8, 16)):
     """Sparse versus dense (Fig. 7): a 100k x 100k matrix with a fixed share
     of distinct random columns in every row times a 100k x 64 B, SpMM (plan by
@@ -1368,6 +1397,21 @@ def main():
                                                         / 1e9, 1),
                                       "frac": row["gather_model_frac"]}},
     }
+    if not args.quick:
+        # the same kernel against the measured ceiling of its access to B:
+        # random rows of B's row size from a table of B's size, nothing else
+        eb = {"f32": 4, "bf16": 2, "f16": 2}[args.dtype]
+        ceil = live_gather_ceiling(n * eb, A.k * n * eb)
+        if ceil:
+            got = A.nnz / (kavg * 1e-3)
+            out["roofline"]["gather_ceiling"] = {
+                "achieved_rows_per_s": round(got / 1e9, 2), "ceiling_rows_per_s":
+                round(ceil["rows_per_s"] / 1e9, 2), "unit": "G rows/s",
+                "frac": round(got / ceil["rows_per_s"], 4), "row_bytes": ceil["row_bytes"],
+                "table_bytes": ceil["table_bytes"],
+                "source": "spmm_calibrate_gather measured in this run: random rows of B's row "
+                          "size read from a table of about B's size, with no reads of A and "
+                          "no writes of C"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, n)
     if not args.quick:
