@@ -229,9 +229,11 @@ __global__ __launch_bounds__(kBlock) void k_rowblock(const int* __restrict__ row
                 const int nvalid = (cnt - slot + TS - 1) >> ts_log2;  // this slot's entries
                 const int* sw = s_w + ebase + (slot << (g_log2 + 1));
                 const float* sv = s_v + (ebase + (slot << (g_log2 + 1))) * RB;
-                // Whole steps of U entries, two in flight: the gathers of step
-                // k + U are issued before the adds of step k wait for theirs
-                // (the adds keep the entry order).
+                // Whole steps of U entries. From U = 4 on two are in flight: the
+                // gathers of step k + U are issued before the adds of step k wait
+                // for theirs (the adds keep the entry order); below that one at a
+                // time (two steps of two rows hold no more rows in flight than
+                // one of four, and cost registers and loop work).
                 auto gather = [&](int k0, uint32_t (&w)[U], float (&bv)[U][VEC]) {
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
@@ -256,7 +258,14 @@ __global__ __launch_bounds__(kBlock) void k_rowblock(const int* __restrict__ row
                     }
                 };
                 int k = 0;
-                if (col_ok && nvalid >= U) {
+                if (U < 4) {
+                    for (; col_ok && k + U <= nvalid; k += U) {
+                        uint32_t w[U];
+                        float bv[U][VEC];
+                        gather(k, w, bv);
+                        add(k, w, bv);
+                    }
+                } else if (col_ok && nvalid >= U) {
                     uint32_t wA[U], wB[U];
                     float bA[U][VEC], bB[U][VEC];
                     gather(0, wA, bA);
