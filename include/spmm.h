@@ -14,7 +14,10 @@
  *
  * Storage types: vals and B share one type - float32, bfloat16 or float16
  * (16-bit types as their bit patterns); they are widened exactly to float32
- * and accumulated in float32. C, dC and dB are always float32.
+ * and accumulated in float32. C, dC and dB are always float32. Where the
+ * forward kernels take bfloat16 entries two at a time (v_dot2_f32_bf16),
+ * bfloat16 values below 2^-126 in magnitude (float32's denormal range) count
+ * as zero.
  *
  * Pointers: every pointer argument is a DEVICE pointer unless its name ends
  * in _host. The caller owns A, B, C and every other array it passes; the
