@@ -1,8 +1,8 @@
 """The largest accepted entry count, nnz = 2^31 - 4097 (entry indices are
 int32 in the kernels; their chunk loops step past an index below nnz by at
-most 4096): row split, merge path, nonzero split and SDDMM on rows whose
-entries reach the top of that range, and merge diagonals past 2^31 (m + nnz
-exceeds int32). Integer values make every product exact: sampled rows (the
+most 4096): row split, merge path, nonzero split, SDDMM, the transpose and
+dB on rows whose entries reach the top of that range, and merge diagonals
+past 2^31 (m + nnz exceeds int32). Integer values make every product exact: sampled rows (the
 last non-empty row holds the largest indices) equal the oracle's bit for
 bit, the three forward kernels agree on every row, the trailing empty rows
 are zero, and the partitions equal the oracle's coordinates."""
@@ -108,4 +108,37 @@ def test_sddmm_at_max_nnz(big):
     assert got[-1023:].size == 1023 and np.array_equal(got[-1023:], ref[-1023:])
     plan.close()
     del dv
+    torch.cuda.empty_cache()
+
+
+def test_transpose_and_dB_at_max_nnz(big):
+    """The radix-sort transpose at 2^31 - 4097 entries (digit histograms and
+    scans at their largest) equals the oracle's counting sort bit for bit,
+    and dB = A^T dC is exact on sampled columns, among them the column of
+    the last entry."""
+    d = big
+    plan = nv.Plan(dev(d["rowptr"]), d["ci"], M, K, N, nnz=MAX_NNZ, mode="paper")
+    plan.transpose_build()
+    at_rp = torch.empty(K + 1, dtype=torch.int32, device="cuda")
+    at_ci = torch.empty(MAX_NNZ, dtype=torch.int32, device="cuda")
+    perm = torch.empty(MAX_NNZ, dtype=torch.int32, device="cuda")
+    nv.spmm_transpose_get(plan.handle, at_rp, at_ci, perm)
+    dB = torch.full((K, N), float("nan"), device="cuda")
+    plan.execute_t(d["vals"], dev(d["dC"]), dB)
+    torch.cuda.synchronize()
+    e_rp, e_ci, e_perm = oracle.transpose(d["rowptr"], d["ci"].cpu().numpy(), K)
+    assert np.array_equal(at_rp.cpu().numpy(), e_rp)
+    assert np.array_equal(at_ci.cpu().numpy(), e_ci)
+    assert np.array_equal(perm.cpu().numpy(), e_perm)
+    del at_ci, perm
+    assert not torch.isnan(dB).any()
+    last_col = int(d["ci"][MAX_NNZ - 1])
+    cols = np.unique(np.array([0, 1, K // 2, K - 1, last_col], np.int64))
+    q = np.concatenate([np.arange(e_rp[c], e_rp[c + 1], dtype=np.int64) for c in cols])
+    v = d["vals"][torch.from_numpy(e_perm[q].astype(np.int64)).cuda()].cpu().numpy()
+    sub_rp = wl.rowptr_from_lengths(e_rp[cols + 1].astype(np.int64) - e_rp[cols])
+    ref = oracle.spmm(sub_rp, e_ci[q], v, d["dC"], k=M).astype(np.float32)
+    assert np.array_equal(dB[torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
+    plan.close()
+    del dB, e_ci, e_perm
     torch.cuda.empty_cache()
