@@ -384,6 +384,8 @@ int spmm_execute_t_scatter(spmm_plan_t plan, const void* A_vals, const float* dC
 
 /* dvals[p] = sum_c dC[row(p), c] * B[colind[p], c] for every stored entry
  * p of A (float32 out, nnz entries). dC is float32, B of the plan's dtype.
+ * The work is split on diagonal merge pieces of 1024 items that the plan
+ * builds at creation (a merge plan with pieces of that size uses its own).
  * Enqueue only. */
 int spmm_sddmm(spmm_plan_t plan, const float* dC, const void* B, float* dvals, void* stream);
 

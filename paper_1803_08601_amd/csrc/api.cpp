@@ -843,9 +843,9 @@ int create_plan(spmm_plan_t* out, const int32_t* rowptr, const int32_t* colind, 
     if (rc == SPMM_OK && p->cfg.kernel == SPMM_KERNEL_ROWSPLIT && p->cfg.col_panels >= 2 &&
         p->m > 0)
         rc = prepare_panels(*p, p->cp, p->cfg.col_panels, st);
-    // SDDMM walks diagonal merge pieces (their row ends fit its LDS); other
-    // plans get such a partition for it.
-    if (rc == SPMM_OK && p->cfg.kernel != SPMM_KERNEL_MERGE && p->m > 0 && p->nnz > 0 &&
+    // SDDMM walks diagonal merge pieces of kSddmmW items (their row ends fit
+    // its LDS); a merge plan of that piece size shares its own partition.
+    if (rc == SPMM_OK && !sddmm_shares_partition(*p) && p->m > 0 && p->nnz > 0 &&
         !(opts && opts->no_sddmm))
         rc = prepare_merge(*p, p->sddmm_ws, kSddmmW, false, st);
     if (rc == SPMM_OK && !(opts && opts->no_sync)) {

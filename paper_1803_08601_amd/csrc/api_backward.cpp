@@ -68,10 +68,13 @@ int spmm_transpose_build(spmm_plan_t plan, void* stream) {
     // The product with A^T runs in float32 (values are widened at gather),
     // planned by the plan's own mode (the MI355X rule for a forced shape, and
     // for a forced row-block plan, whose conditions A^T need not meet).
+    // It never runs SDDMM, so it gets no SDDMM partition.
     const int mode = p.mode >= 0 && p.mode != SPMM_MODE_ROWBLOCK ? p.mode : SPMM_MODE_RULE;
     spmm_plan_s* tp = nullptr;
+    TuneOpts topts;
+    topts.no_sddmm = true;
     int rc = create_plan(&tp, tr.at_rowptr, tr.at_colind, p.k, p.m, p.nnz, p.n, p.ld, SPMM_F32,
-                         mode, nullptr, st, false);
+                         mode, nullptr, st, false, &topts);
     if (rc != SPMM_OK) {
         free_tr();
         return rc;
@@ -120,9 +123,8 @@ int spmm_execute_t_scatter(spmm_plan_t plan, const void* A_vals, const float* dC
     if (!dB) return fail(SPMM_ERR_INVALID, "dB is NULL");
     if (plan->nnz > 0 && (!A_vals || !dC)) return fail(SPMM_ERR_INVALID, "A_vals or dC is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool own = plan->cfg.kernel == SPMM_KERNEL_MERGE;
-    const MergeWs& ws = own ? plan->ws : plan->sddmm_ws;
-    const int W = own ? plan->cfg.items_per_wg : kSddmmW;
+    const MergeWs& ws = sddmm_shares_partition(*plan) ? plan->ws : plan->sddmm_ws;
+    const int W = kSddmmW;
     const int64_t P = plan->nnz > 0 && plan->m > 0 ? ws.P : 0;
     if (P > 0 && !ws.coords) return fail(SPMM_ERR_STATE, "plan has no merge partition");
     hipError_t e = spmmk::launch_scatter_t(plan->dtype, plan->rowptr, plan->colind, A_vals, dC, dB,
@@ -145,9 +147,8 @@ int spmm_sddmm(spmm_plan_t plan, const float* dC, const void* B, float* dvals, v
     if (vec != 1 && (!aligned16(dC) || !aligned16(B))) vec = 1;
     int g_log2, col_tiles;
     slot_geometry(plan->n, vec, &g_log2, &col_tiles);
-    const bool own = plan->cfg.kernel == SPMM_KERNEL_MERGE;
-    const MergeWs& ws = own ? plan->ws : plan->sddmm_ws;
-    const int W = own ? plan->cfg.items_per_wg : kSddmmW;
+    const MergeWs& ws = sddmm_shares_partition(*plan) ? plan->ws : plan->sddmm_ws;
+    const int W = kSddmmW;
     if (!ws.coords) return fail(SPMM_ERR_STATE, "plan has no merge partition for SDDMM");
     hipError_t e = spmmk::launch_sddmm(plan->dtype, vec, sddmm_unroll(vec), g_log2, col_tiles,
                                        plan->rowptr, plan->colind, dC, B, dvals, plan->n,

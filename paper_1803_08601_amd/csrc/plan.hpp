@@ -65,7 +65,7 @@ struct spmm_plan_s {
     double tuned_ms = 0.0;
     int device = 0;
     spmmh::MergeWs ws;
-    spmmh::MergeWs sddmm_ws;  // merge partition for SDDMM when the kernel is row split
+    spmmh::MergeWs sddmm_ws;  // SDDMM's partition unless the plan's own serves (kSddmmW)
     spmmh::RowBlocks rb;      // ROWBLOCK plans
     spmmh::ColPanels cp;      // row-split plans with column panels
     int sorted = -1;          // columns strictly increase in every row: 1 / 0 / -1 unknown
@@ -84,9 +84,19 @@ struct spmm_plan_s {
 
 namespace spmmh {
 
-// Merge items per workgroup of the SDDMM kernel when the plan has no merge
-// partition of its own.
-constexpr int kSddmmW = 2048;
+// Merge items per workgroup of the SDDMM kernel (and of the atomic dB
+// scatter). Timed on the GCN and power-law matrices at n = 64 and 128 in
+// FP32 and BF16, pieces of 512 to 1024 items were 3-6 % faster than 2048
+// (more workgroups per CU for the 8 KB of staged row ends and columns)
+// and 256 slower again. A merge plan with pieces of this size shares its
+// own partition; every other plan gets one at creation.
+constexpr int kSddmmW = 1024;
+
+// Whether SDDMM and the atomic dB scatter run on the plan's own partition:
+// a merge plan (diagonal pieces) whose pieces hold kSddmmW items.
+inline bool sddmm_shares_partition(const spmm_plan_s& p) {
+    return p.cfg.kernel == SPMM_KERNEL_MERGE && p.cfg.items_per_wg == kSddmmW;
+}
 
 bool plan_alive(const spmm_plan_s* p);
 bool aligned16(const void* ptr);
@@ -108,7 +118,7 @@ struct TuneOpts {
     // no statistics pass
     bool known_stats = false;
     int64_t max_row_len = 0, long_rows = 0;
-    bool no_sddmm = false;  // no SDDMM partition for a row-split plan
+    bool no_sddmm = false;  // no SDDMM partition (a plan that never runs SDDMM)
     bool no_sync = false;   // do not synchronise the stream at the end
     bool no_planes = false; // no plane-structure pass (the tile order stays the row order)
     const void* vals = nullptr;

@@ -90,8 +90,9 @@ def test_every_launch_shape(matrix, dtype, n):
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
 @pytest.mark.parametrize("n", [1, 3, 8, 24, 64, 72, 136])
 def test_sddmm_every_launch_shape(matrix, dtype, n):
-    """SDDMM walks diagonal pieces: the plan's own merge pieces (any size) or
-    a fixed partition of its own; every vector width and piece size."""
+    """SDDMM walks diagonal pieces of 1024 items: the plan's own when it is a
+    merge plan of that piece size, else a partition built with the plan;
+    every vector width and plan shape."""
     import oracle
     from spmm_check import host_bits
 
@@ -103,7 +104,7 @@ def test_sddmm_every_launch_shape(matrix, dtype, n):
     ref = oracle.sddmm(A.rowptr, A.colind, dC, b, b_tag=btag)
     N = oracle.sddmm(A.rowptr, A.colind, dC, b, b_tag=btag, absval=True)
     v16 = VEC16[dtype]
-    shapes = [dict(kernel=MG, items_per_wg=W) for W in (64, 100, 1000, 4096)]
+    shapes = [dict(kernel=MG, items_per_wg=W) for W in (64, 100, 1000, 1024, 4096)]
     shapes += [dict(kernel=RS), dict(kernel=NZ, items_per_wg=1000), dict(kernel=RB)]
     dv = torch.empty(A.nnz, device="cuda")
     ran = 0
