@@ -115,6 +115,26 @@ def test_stencil_integer_exact_full(stencil, n):
         plan.close()
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("mode", ["autotune", "merge", "nzsplit"])
+def test_power_law_16bit_storage_full(power_law, dtype, mode):
+    """16-bit storage of vals and B at full size (the benchmark's BF16 row
+    plans by timing): sampled rows against the oracle on the same 16-bit
+    inputs, within the float32 accumulation bound."""
+    A = power_law
+    n = 64
+    vt = dev(A.vals).to(DT[dtype])
+    Bt = dev(wl.dense(1002, A.k, n)).to(DT[dtype])
+    plan = nv.Plan(dev(A.rowptr), dev(A.colind), A.m, A.k, n, dtype=nv.dtype_code(DT[dtype]),
+                   mode=mode, nnz=A.nnz)
+    C = torch.full((A.m, n), float("nan"), device="cuda")
+    plan.execute(vt, Bt, C)
+    torch.cuda.synchronize()
+    assert not torch.isnan(C).any()
+    check_rows(A, vt, Bt, C, n, sample_rows(A))
+    plan.close()
+
+
 def test_power_law_integer_exact_full(power_law):
     """Integer values at full size: the whole output must equal the oracle
     bit for bit, whatever the kernel and order."""
