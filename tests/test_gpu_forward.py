@@ -76,6 +76,27 @@ def test_plain_configs(cfg, n):
     check(A, dev(A.vals), dev(B), n, C)
 
 
+@pytest.mark.parametrize("mode", ["autotune", "paper", "rule"])
+def test_uniform_4096_workload_whole_output(mode):
+    """The uniform 4096 x 4096 workload with 16 entries per row at n = 32 (the
+    launch-bound case the benchmark times, planned the same way): the whole
+    output against the oracle, and on integer values bit for bit."""
+    A = wl.plain()
+    assert (A.m, A.k, A.nnz) == (4096, 4096, 65536)
+    n = 32
+    B = wl.dense(1001, A.k, n)
+    C, plan = run(A, dev(A.vals), dev(B), n, mode=mode)
+    check(A, dev(A.vals), dev(B), n, C)
+    Ai = wl.CSR(A.rowptr, A.colind,
+                np.random.default_rng(5).integers(-8, 9, A.nnz).astype(np.float32), A.m, A.k)
+    Bi = wl.dense(1002, A.k, n, kind="int")
+    Ci = torch.full((A.m, n), float("nan"), device="cuda")
+    plan.execute(dev(Ai.vals), dev(Bi), Ci)
+    torch.cuda.synchronize()
+    assert np.array_equal(Ci.cpu().numpy(), oracle.spmm(A.rowptr, A.colind, Ai.vals, Bi).astype(np.float32))
+    plan.close()
+
+
 @pytest.mark.parametrize("mode", ["paper", "rowsplit", "merge", "nzsplit", "rowblock", "autotune"])
 def test_power_law_modes(mode):
     A = wl.power_law(seed=31, m=40_000, cap=20_000)
