@@ -114,6 +114,7 @@ int spmm_batch_plan(spmm_batch_t* out_batch, const spmm_problem* problems_host, 
         opts.rowblock = false;  // the persistent kernel runs row split and merge tiles only
         opts.panels = false;    // ... each in one pass
         opts.no_planes = true;  // ... in its own order of work items
+        opts.no_sddmm = true;   // the batch runs forward products only
         opts.vals = q.A_vals;
         opts.B = q.B;
         opts.C = q.C;
