@@ -139,9 +139,9 @@ int spmm_sddmm(spmm_plan_t plan, const float* dC, const void* B, float* dvals, v
     if (!dvals) return fail(SPMM_ERR_INVALID, "dvals is NULL");
     if (plan->n > 0 && (!dC || !B)) return fail(SPMM_ERR_INVALID, "dC or B is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (plan->n == 0) {
-        SPMM_HIP(hipMemsetAsync(dvals, 0, sizeof(float) * plan->nnz, st));
-        return SPMM_OK;
+    if (plan->n == 0) {  // every dot product is empty
+        const hipError_t e = spmmk::launch_zero_f32(dvals, plan->nnz, st);
+        return e == hipSuccess ? SPMM_OK : hip_fail(e, "SDDMM zero fill");
     }
     int vec = plan->cfg.vec;
     if (vec != 1 && (!aligned16(dC) || !aligned16(B))) vec = 1;

@@ -543,6 +543,13 @@ __global__ __launch_bounds__(kBlock) void k_zero_rows(float* __restrict__ a, int
         a[(q / n) * ld + q % n] = 0.f;
 }
 
+hipError_t launch_zero_f32(float* a, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_rows, dim3(grid_for(count)), dim3(kBlock), 0, st, a, count, 1,
+                       int64_t(1));
+    return hipGetLastError();
+}
+
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_scatter_t(const int* __restrict__ rowptr,
                                                        const int* __restrict__ colind,

@@ -104,14 +104,17 @@ int64_t transpose_scratch_len(int64_t nnz);
 hipError_t launch_gather_widen(int dtype, const void* vals, const int* perm, int64_t n,
                                float* out, hipStream_t st);
 
-// dvals[p] = <dC[row(p), :n], B[colind[p], :n]> over the P merge pieces of W
-// items given by coords (2 * (P + 1) ints).
 // dB = A^T dC by float atomic adds on diagonal merge pieces (dB is zeroed
 // first); not bitwise repeatable.
 hipError_t launch_scatter_t(int dtype, const int* rowptr, const int* colind, const void* vals,
                             const float* dC, float* dB, int64_t k, int64_t n, int64_t ld,
                             const int* coords, int64_t P, int W, hipStream_t st);
 
+// a[0 .. count) = 0 by a kernel (no memset node when the stream is captured).
+hipError_t launch_zero_f32(float* a, int64_t count, hipStream_t st);
+
+// dvals[p] = <dC[row(p), :n], B[colind[p], :n]> over the P merge pieces of W
+// items given by coords (2 * (P + 1) ints).
 hipError_t launch_sddmm(int dtype, int vec, int unroll, int g_log2, int col_tiles,
                         const int* rowptr, const int* colind, const float* dC, const void* B,
                         float* dvals, int64_t n, int64_t ld, const int* coords, int64_t P, int W,

@@ -134,3 +134,15 @@ def test_noalloc_replays():
     B = dev(wl.dense(88, A.k, n, kind="int"))
     C = torch.empty(A.m, n, device="cuda")
     _replays(lambda: nv.spmm_csr_noalloc(rp, ci, vals, B, C, A.m, A.k, A.nnz, n, n), [C], vals)
+
+
+def test_sddmm_without_columns_replays():
+    """SDDMM with n = 0 (every dot product empty) writes zeros by a kernel,
+    so a captured call clears dvals again on every replay."""
+    A = POWER
+    rp, ci = dev(A.rowptr), dev(A.colind)
+    plan = nv.Plan(rp, ci, A.m, A.k, 0, ld=1, nnz=A.nnz)
+    dv = torch.empty(A.nnz, device="cuda")
+    _replays(lambda: nv.spmm_sddmm(plan.handle, None, None, dv), [dv], torch.zeros(1, device="cuda"))
+    assert torch.all(dv == 0)
+    plan.close()
